@@ -1,0 +1,373 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every oracle function is checked here against something other than itself:
+brute force, closed forms, special cases, invariants, finite differences and
+the paper's one comparative claim (block-diagonal SPC converges where
+diagonal SPC does not, Sec. III).  A few tests plant a mistake in a copy of
+an oracle step and check that the pin catches it.
+"""
+import warnings
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from helpers import micro_problem, rotation
+from oracle import model, mocca, projector as pj, spc
+
+warnings.filterwarnings("ignore", category=RuntimeWarning)
+
+
+# ------------------------------------------------------------ inputs (synth)
+
+def test_attenuation_check_values():
+    # mu_m(E) = a (E/30)^-3 kappa + b KN(E)/KN(30): at 30 keV exactly a + b.
+    mu = synth.attenuation_table([30.0, 50.0, 51.0, 80.0])
+    np.testing.assert_allclose(mu[:, 0], [0.22, 0.73, 30.9], rtol=1e-12)
+    np.testing.assert_allclose(mu[:, 1:], [[0.192, 0.191, 0.174], [0.433, 0.427, 0.347],
+                                           [7.326, 31.375, 8.689]], atol=1.5e-3)
+    # the Gd photo-electric term jumps x5 across 50.2 keV
+    e = np.array([50.0, 51.0])
+    ph = mu[2, 1:3] - 0.9 * synth.klein_nishina(e) / synth.klein_nishina(30.0)
+    np.testing.assert_allclose(ph[1] / ph[0], 5.0 * (50.0 / 51.0) ** 3, rtol=1e-12)
+
+
+def test_spectral_response_normalised():
+    sp_ = synth.make_spectral(20, 119, 120.0, 1e5)
+    np.testing.assert_allclose(sp_.s.sum(axis=1), 1.0, rtol=1e-14)
+    assert (sp_.s >= 0).all()
+    # four overlapping windows: every adjacent pair shares energies
+    for w in range(3):
+        assert (np.minimum(sp_.s[w], sp_.s[w + 1]) > 1e-4).any()
+
+
+# ------------------------------------------------------------ projector X
+
+@pytest.mark.parametrize("n,views,bins,view0", [(8, 8, 16, 0.0), (12, 10, 21, 0.3)])
+def test_p1_siddon_equals_bruteforce_clip(n, views, bins, view0):
+    geom = synth.make_geometry(n, 20.0, views, bins)
+    geom = synth.Geometry(**{**geom.__dict__, "view0_rad": view0})
+    Xs = pj.system_matrix(geom).toarray()
+    Xb = pj.dense_matrix_bruteforce(geom)
+    np.testing.assert_allclose(Xs, Xb, atol=1e-12, rtol=0)
+    assert ((Xs > 0) == (Xb > 1e-12)).all()
+
+
+def test_p2_row_sums_are_square_chords():
+    geom = synth.make_geometry(64, 20.0, 64, 128)
+    X = pj.system_matrix(geom)
+    rho = np.asarray(X.sum(axis=1)).ravel()
+    ref = pj.square_chord(geom)
+    np.testing.assert_allclose(rho, ref, rtol=1e-12, atol=1e-12)
+    assert (ref == 0).any() and (ref > 0).mean() > 0.85    # edge bins miss the square
+
+
+def test_p3_disk_chords():
+    geom = synth.make_geometry(64, 20.0, 16, 64)
+    X = pj.system_matrix(geom)
+    cx, cy, r = 3.0, -2.0, 5.0
+    disk = synth.disk_phantom(64, 20.0, [(cx, cy, r, (1.0, 0, 0))], (0.0, 0, (0, 0, 0)))[0].ravel()
+    p = X @ disk
+    chord, dist = pj.disk_chord(geom, cx, cy, r)
+    sel = dist < r - 2 * geom.pixel_cm
+    assert sel.sum() > 100
+    assert np.abs(p - chord)[sel].max() < geom.pixel_cm
+    # a mirrored disk (wrong sign of one axis) is far off: the pin sees flips
+    wrong, _ = pj.disk_chord(geom, cx, -cy, r)
+    assert np.abs(p - wrong)[sel].max() > 10 * geom.pixel_cm
+
+
+def test_p4_adjoint():
+    geom = synth.make_geometry(32, 20.0, 24, 48)
+    X = pj.system_matrix(geom)
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal(X.shape[1]); g = rng.standard_normal(X.shape[0])
+    lhs = np.dot(X @ f, g); rhs = np.dot(f, X.T @ g)
+    assert abs(lhs - rhs) <= 1e-12 * np.abs(X).sum()
+
+
+def test_p5_rotation_and_mirror_symmetry():
+    geom = synth.make_geometry(64, 20.0, 16, 64)
+    X = pj.system_matrix(geom)
+    rng = np.random.default_rng(5)
+    f = rng.random((64, 64))
+    p = (X @ f.ravel()).reshape(16, 64)
+    # the scan rotated by a quarter turn sees the image rotated by a quarter turn
+    pr = (X @ np.rot90(f, -1).ravel()).reshape(16, 64)
+    np.testing.assert_allclose(np.roll(pr, -4, axis=0), p, atol=1e-11)
+    # mirror y -> -y maps view beta to -beta and bin u to -u
+    pm = (X @ f[::-1, :].ravel()).reshape(16, 64)
+    np.testing.assert_allclose(pm[(-np.arange(16)) % 16, ::-1], p, atol=1e-11)
+
+
+def test_pixel_column_matches_matrix():
+    geom = synth.make_geometry(24, 20.0, 12, 40)
+    X = pj.system_matrix(geom).tocsc()
+    for ix, iy in [(0, 0), (5, 17), (23, 11)]:
+        col = pj.pixel_column(geom, ix, iy)
+        np.testing.assert_allclose(col, X[:, iy * 24 + ix].toarray().ravel(), atol=1e-12)
+
+
+# ------------------------------------------------------------ counts model
+
+def test_softexp_shape_and_cond1():
+    x = np.linspace(-5, 5, 2001)
+    assert np.all(model.softexp_d2(x) <= model.softexp_d1(x))          # Eq. (cond1)
+    np.testing.assert_allclose(model.softexp(x[x <= 0]), np.exp(x[x <= 0]))
+    np.testing.assert_allclose(model.softexp(x[x > 0]), x[x > 0] + 1)
+    # value and slope continuous at 0, curvature jumps
+    h = 1e-7
+    assert abs(model.softexp(h) - model.softexp(-h)) < 3e-7
+    assert abs(model.softexp_d1(h) - model.softexp_d1(-h)) < 3e-7
+    assert model.softexp_d2(0.0) == 1.0 and model.softexp_d2(h) == 0.0
+
+
+def test_p8_zero_attenuation():
+    _, spec, _ = micro_problem()
+    p = np.zeros((5, 3))
+    chat = model.counts_model(p, spec)
+    np.testing.assert_allclose(chat, np.broadcast_to(spec.n0, chat.shape), rtol=1e-15)
+    A, B, g = model.matrices_AB(p, spec)
+    np.testing.assert_allclose(A, np.broadcast_to(spec.s, A.shape), rtol=1e-15)
+    np.testing.assert_allclose(B, A, rtol=1e-15)
+    G = model.ray_jacobian(p, spec)
+    np.testing.assert_allclose(G[0], spec.s @ spec.mu.T, rtol=1e-14)
+
+
+def test_p8_standard_model_agrees_for_physical_paths():
+    _, spec, _ = micro_problem()
+    rng = np.random.default_rng(8)
+    p = rng.random((50, 3)) * np.array([10.0, 1.0, 0.01])
+    np.testing.assert_allclose(model.counts_model(p, spec), model.counts_model_standard(p, spec), rtol=1e-14)
+
+
+def test_p9_monochromatic_beer_lambert():
+    mu, length, n0 = 0.3, 2.0, 1e4
+    spec = synth.Spectral(mu=np.array([[mu]]), s=np.array([[1.0]]), n0=np.array([n0]))
+    X = sp.csr_matrix(np.array([[length]]))
+    f_star = 1.7
+    c = np.array([[n0 * np.exp(-mu * length * f_star)]])
+    # the counts model is Beer-Lambert
+    np.testing.assert_allclose(model.counts_model(np.array([[length * f_star]]), spec), c, rtol=1e-14)
+    for pre in ("block", "diag"):
+        for cur in ("clip", "window"):
+            st, _ = mocca.mocca(X, c, spec, 1e-4, 300, pre, cur)
+            np.testing.assert_allclose(st.f.ravel(), [np.log(n0 / c[0, 0]) / (mu * length)], rtol=1e-10)
+
+
+def test_p10_gradient_by_finite_differences():
+    geom, spec, f_true = micro_problem()
+    X = pj.system_matrix(geom)
+    c = model.counts_model(X @ f_true.reshape(3, -1).T, spec) * 1.02
+    rng = np.random.default_rng(10)
+    f = f_true.reshape(3, -1) * (1 + 0.05 * rng.standard_normal((3, 256)))
+    f[0] += 0.05            # keep every (Zf) > 0: softexp'' jumps at 0, which spoils central differences
+    grad = model.image_gradient(X, f, c, spec)
+    for _ in range(3):
+        d = rng.standard_normal(f.shape) * np.array([[1.0], [0.1], [0.001]])
+        h = 1e-5
+        fd = (model.image_objective(X, f + h * d, c, spec) - model.image_objective(X, f - h * d, c, spec)) / (2 * h)
+        assert abs(fd - np.sum(grad * d)) <= 1e-7 * abs(fd) + 1e-9
+
+
+def test_p10_hessian_by_finite_differences():
+    _, spec, _ = micro_problem()
+    rng = np.random.default_rng(11)
+    p = 0.5 + rng.random((20, 3)) * np.array([10.0, 1.0, 0.01])        # z > 0 on every energy
+    c = model.counts_model(p, spec) * (1 + 0.1 * rng.standard_normal((20, 4)))
+    H = model.hessian_p(p, c, spec)
+    for m in range(3):
+        h = 1e-5 * max(1.0, abs(p[:, m]).max())
+        e = np.zeros(3); e[m] = h
+        fd = (model.gradient_p(p + e, c, spec) - model.gradient_p(p - e, c, spec)) / (2 * h)
+        np.testing.assert_allclose(fd, H[:, :, m], rtol=1e-6, atol=1e-6 * np.abs(H).max())
+    # H is symmetric and, for c > chat on some windows, indefinite in places
+    np.testing.assert_allclose(H, np.swapaxes(H, 1, 2), rtol=1e-12)
+
+
+def test_p10_C_nonnegative_and_A_row_sums():
+    _, spec, _ = micro_problem()
+    rng = np.random.default_rng(12)
+    p = rng.standard_normal((200, 3)) * np.array([5.0, 1.0, 0.02])      # mixed signs: both branches
+    A, B, g = model.matrices_AB(p, spec)
+    assert (A - B >= 0).all()                                           # C = A - B >= 0
+    assert (A.sum(axis=2) <= 1 + 1e-14).all()
+
+
+def test_p14_deviance_statistics():
+    from oracle import projector
+    pr = synth.problem("tiny")
+    X = projector.system_matrix(pr.geom)
+    chat = model.counts_model(X @ pr.f_true.reshape(3, -1).T, pr.spec)
+    c = synth.poisson_counts(chat, pr.seed)
+    dev = 2 * model.dtpl(c, chat)
+    wl = c.size
+    assert abs(dev - wl) < 4 * np.sqrt(2 * wl)
+
+
+# ------------------------------------------------------------ step lengths
+
+def _random_tiny_K(seed, signed):
+    rng = np.random.default_rng(seed)
+    L, W, M, P = 12, 4, 3, 9
+    X = rng.random((L, P)) * (rng.random((L, P)) < 0.5)
+    G = rng.standard_normal((L, W, M)) if signed else rng.random((L, W, M))
+    return G, X
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_p6_factored_steps_equal_dense_definitions(signed):
+    G, X = _random_tiny_K(6, signed)
+    lam = 0.37
+    K = spc.dense_K(G, X)
+    rho = X.sum(axis=1)
+    sig_inv_d, tinv_d = spc.block_steps_dense(K, lam, 3)
+    sig_f, tinv_f = spc.block_steps_factored(G, sp.csr_matrix(X), rho, lam)
+    np.testing.assert_allclose(1.0 / sig_f.T.ravel(), sig_inv_d, rtol=1e-12)
+    np.testing.assert_allclose(tinv_f, tinv_d, rtol=1e-12, atol=1e-14)
+    sig_d, tau_d = spc.diag_steps_dense(K, lam, 3)
+    sig_f, tau_f = spc.diag_steps_factored(G, sp.csr_matrix(X), rho, lam)
+    np.testing.assert_allclose(sig_f.T.ravel(), sig_d, rtol=1e-12)
+    np.testing.assert_allclose(tau_f.T.ravel(), tau_d, rtol=1e-12)
+
+
+def test_p6_on_model_jacobian():
+    geom, spec, f_true = micro_problem(n=8, views=6, bins=12)
+    X = pj.system_matrix(geom)
+    p = X @ f_true.reshape(3, -1).T
+    G = model.ray_jacobian(p, spec)
+    rho = np.asarray(X.sum(axis=1)).ravel()
+    keep = rho > 0
+    K = spc.dense_K(G[keep], X.toarray()[keep])
+    sig_inv_d, tinv_d = spc.block_steps_dense(K, 1e-3, 3)
+    sig_f, tinv_f = spc.block_steps_factored(G[keep], X[keep], rho[keep], 1e-3)
+    np.testing.assert_allclose(1.0 / sig_f.T.ravel(), sig_inv_d, rtol=1e-12)
+    np.testing.assert_allclose(tinv_f, tinv_d, rtol=1e-12)
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_p7_step_matrix_psd(signed):
+    G, X = _random_tiny_K(7, signed)
+    K = spc.dense_K(G, X)
+    for lam in (0.01, 1.0, 30.0):
+        sig_inv, tinv = spc.block_steps_dense(K, lam, 3)
+        M = spc.assemble_M(K, tinv_blocks=tinv, sigma_inv=sig_inv)
+        assert np.linalg.eigvalsh(M).min() >= -1e-12 * np.abs(M).max()
+        sig, tau = spc.diag_steps_dense(K, lam, 3)
+        M = spc.assemble_M(K, tau=tau, sigma=sig)
+        assert np.linalg.eigvalsh(M).min() >= -1e-12 * np.abs(M).max()
+    # planted mistake: dropping the 1/|K| normalisation breaks the condition
+    R = K.shape[0]; P = K.shape[1] // 3
+    Kr = K.reshape(R, 3, P)
+    bad = np.einsum("rmk,rnk->kmn", Kr, Kr) * 0.5 / np.abs(K).max()
+    M = spc.assemble_M(K, tinv_blocks=bad, sigma_inv=spc.block_steps_dense(K, 1.0, 3)[0])
+    assert np.linalg.eigvalsh(M).min() < -1e-6
+
+
+# ------------------------------------------------------------ curvature, prox
+
+def test_p11_negative_curvature_clip():
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((50, 3, 3)); H = A + np.swapaxes(A, 1, 2)
+    Hp = mocca.clip_negative_curvature(H)
+    assert np.linalg.eigvalsh(Hp).min() > -1e-12
+    assert np.linalg.eigvalsh(Hp - H).min() > -1e-12                # an upper bound of H
+    # the nearest PSD matrix in Frobenius norm: no random PSD candidate is closer
+    for _ in range(20):
+        B = rng.standard_normal((50, 3, 3)); P = Hp + 0.1 * B @ np.swapaxes(B, 1, 2)
+        assert (np.linalg.norm(H - P, axis=(1, 2)) >= np.linalg.norm(H - Hp, axis=(1, 2)) - 1e-12).all()
+    S = A @ np.swapaxes(A, 1, 2)                                      # already PSD: unchanged
+    np.testing.assert_allclose(mocca.clip_negative_curvature(S), S, atol=1e-12)
+    # 2x2 block diag(a, -b) -> diag(a, 0)
+    np.testing.assert_allclose(mocca.clip_negative_curvature(np.diag([2.0, -3.0, 1.0])),
+                               np.diag([2.0, 0.0, 1.0]), atol=1e-15)
+
+
+def test_p11_clip_curvature_reproduces_clipped_hessian():
+    rng = np.random.default_rng(12)
+    G = rng.standard_normal((30, 4, 3))
+    A = rng.standard_normal((30, 3, 3)); H = A + np.swapaxes(A, 1, 2)
+    D = mocca.curvature_clip(G, H)
+    np.testing.assert_allclose(np.swapaxes(G, 1, 2) @ D @ G, mocca.clip_negative_curvature(H), atol=1e-10)
+    assert np.linalg.eigvalsh(D).min() > -1e-10
+
+
+def test_p11_dual_prox_optimality_and_moreau():
+    rng = np.random.default_rng(13)
+    L, W = 40, 4
+    B = rng.standard_normal((L, W, 3)); D = B @ np.swapaxes(B, 1, 2)   # PSD rank 3
+    sigma = rng.random((L, W)) + 0.1
+    v, u0, r = rng.standard_normal((3, L, W))
+    y = mocca.dual_prox(v, u0, sigma, r, D)
+    u = (v - y) / sigma
+    np.testing.assert_allclose(y, r + np.einsum("lwv,lv->lw", D, u - u0), atol=1e-12)
+    # Moreau: y = v - Sigma prox_{Sigma^-1 Q}(Sigma^-1 v); the primal prox solves
+    # grad Q(u) + Sigma (u - Sigma^-1 v) = 0
+    lhs = D + sigma[:, :, None] * np.eye(W)[None]
+    u_p = np.linalg.solve(lhs, (v - r + np.einsum("lwv,lv->lw", D, u0))[..., None])[..., 0]
+    np.testing.assert_allclose(y, v - sigma * u_p, atol=1e-12)
+    # window curvature with v = y_n + Sigma u0: y = (c y_n + sigma r) / (c + sigma)
+    c = rng.random((L, W)) * 10 + 1
+    yn = rng.standard_normal((L, W))
+    yw = mocca.dual_prox(yn + sigma * u0, u0, sigma, r, mocca.curvature_window(c))
+    np.testing.assert_allclose(yw, (c * yn + sigma * r) / (c + sigma), rtol=1e-12)
+
+
+# ------------------------------------------------------------ MOCCA iterations
+
+@pytest.fixture(scope="module")
+def micro():
+    geom, spec, f_true = micro_problem()
+    X = pj.system_matrix(geom)
+    c = model.counts_model(X @ f_true.reshape(3, -1).T, spec)
+    return geom, spec, f_true.reshape(3, -1), X, c
+
+
+@pytest.mark.parametrize("curv", ["clip", "window"])
+def test_p12_block_spc_rotation_equivariant(micro, curv):
+    geom, spec, f_true, X, c = micro
+    R = rotation(3)
+    spec_r = synth.Spectral(mu=R @ spec.mu, s=spec.s, n0=spec.n0)
+    lam = 2e-7
+    st, _ = mocca.mocca(X, c, spec, lam, 20, "block", curv)
+    st_r, _ = mocca.mocca(X, c, spec_r, lam, 20, "block", curv)
+    np.testing.assert_allclose(st_r.f, R @ st.f, rtol=0, atol=1e-9 * np.abs(st.f).max())
+    # diagonal SPC is not: the paper's motivation for the block form
+    sd, _ = mocca.mocca(X, c, spec, lam, 20, "diag", curv)
+    sd_r, _ = mocca.mocca(X, c, spec_r, lam, 20, "diag", curv)
+    assert np.abs(sd_r.f - R @ sd.f).max() > 1e-4 * np.abs(sd.f).max()
+
+
+@pytest.mark.parametrize("pre", ["block", "diag"])
+@pytest.mark.parametrize("curv", ["clip", "window"])
+def test_p13_truth_is_a_fixed_point(micro, pre, curv):
+    geom, spec, f_true, X, c = micro
+    st, _ = mocca.mocca(X, c, spec, 2e-7, 5, pre, curv, f0=f_true)
+    np.testing.assert_allclose(st.f, f_true, atol=1e-10)
+    assert np.abs(st.y).max() < 1e-6
+
+
+def test_p13_noiseless_descent(micro):
+    geom, spec, f_true, X, c = micro
+    d0 = model.image_objective(X, np.zeros_like(f_true), c, spec)
+    st, hist = mocca.mocca(X, c, spec, 2e-7, 150, "block", "clip", dtpl_every=50)
+    assert hist[-1][1] < 1e-3 * d0
+
+
+def test_claim_block_spc_beats_diagonal_spc(micro):
+    """Sec. III: with lambda tuned per method, block-diagonal SPC reaches a far
+    lower D_TPL than diagonal SPC (which the paper reports as divergent)."""
+    geom, spec, f_true, X, c = micro
+    best = {}
+    for pre in ("block", "diag"):
+        vals = []
+        for lam in (1e-7, 2e-7, 4e-7, 8e-7, 1.6e-6):
+            try:
+                st, hist = mocca.mocca(X, c, spec, lam, 100, pre, "clip", dtpl_every=100)
+                d = hist[-1][1]
+                vals.append(d if np.isfinite(d) else np.inf)
+            except np.linalg.LinAlgError:
+                vals.append(np.inf)
+        best[pre] = min(vals)
+    assert best["block"] < 0.1 * best["diag"]
