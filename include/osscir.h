@@ -1,0 +1,196 @@
+/*
+ * osscir.h -- C ABI of the MI355X (gfx950) library for one-step spectral-CT
+ * image reconstruction (OSSCIR) by MOCCA with diagonal or m-block-diagonal
+ * step preconditioning (Sidky, Barber, Gilat-Schmidt, Pan, arXiv 1801.06263).
+ *
+ * Problem (Sec. II): given measured counts c_{w,l} in W energy windows along
+ * rays l, normalised window responses s_{w,i}, incident counts N_w, material
+ * attenuation mu_{m,i} and the scan geometry (which fixes the projection
+ * X_{l,k}), recover material maps f_{k,m} by minimising
+ * D_TPL(c, chat(f)) with the softexp counts model (Eq. finalModel).
+ *
+ * Conventions shared by every call
+ *  - Image arrays are [n_ch][n][n] float32, x fastest; pixel (ix, iy) is
+ *    centred at ((ix-(n-1)/2) h, (iy-(n-1)/2) h), h = pixel_cm.
+ *  - Sinogram arrays are [n_ch][n_views][n_bins] float32, bin fastest; ray
+ *    l = v*n_bins + d; L = n_views*n_bins.
+ *  - Every data pointer argument is a DEVICE pointer owned by the caller
+ *    (allocated on the device the plan was created on), unless documented
+ *    "host".  The library allocates device memory only inside
+ *    osscir_plan_create (its constant tables and ray geometry) and frees it
+ *    in osscir_plan_destroy; it keeps no pointer to caller memory after a
+ *    call returns.
+ *  - Calls that take a stream enqueue their work asynchronously on it (NULL =
+ *    the null stream) and return without synchronising.  Only
+ *    osscir_plan_create and osscir_plan_destroy synchronise.
+ *  - Return codes: OSSCIR_OK (0), OSSCIR_EINVAL (-1: null pointer, bad size,
+ *    unsupported material/window count), OSSCIR_EDEVICE (-2: a HIP call or
+ *    launch failed), OSSCIR_ENOMEM (-3), OSSCIR_ESTATE (-4: workspace too
+ *    small).  osscir_last_error() returns the calling thread's last message.
+ *  - A plan may be used from one host thread at a time; different plans are
+ *    independent.  Results are deterministic: no floating-point atomics, fixed
+ *    accumulation order.
+ */
+#ifndef OSSCIR_H
+#define OSSCIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OSSCIR_OK 0
+#define OSSCIR_EINVAL (-1)
+#define OSSCIR_EDEVICE (-2)
+#define OSSCIR_ENOMEM (-3)
+#define OSSCIR_ESTATE (-4)
+
+#define OSSCIR_PRECOND_DIAG 0   /* diagonal SPC (Pock-Chambolle), Sec. II "Step lengths" */
+#define OSSCIR_PRECOND_BLOCK 1  /* m-block-diagonal SPC, Sec. II "A m-block diagonal SPC" */
+
+#define OSSCIR_CURV_WINDOW 0    /* local quadratic curvature diag(c_l) */
+#define OSSCIR_CURV_CLIP 1      /* per-ray Hessian with negative curvature removed */
+
+typedef struct osscir_plan_s *osscir_plan;
+typedef void *osscir_stream; /* a hipStream_t */
+
+/* Fan-beam scan with a flat detector.  View v has source angle
+ * beta_v = view0_rad + arc_rad * v / n_views, source at sid_cm (cos, sin),
+ * detector centre at -(sdd_cm - sid_cm)(cos, sin), detector axis
+ * (-sin, cos), bin d centred at (d - (n_bins-1)/2) * bin_cm.  The ray of
+ * (v, d) joins the source to the bin centre; X_{l,k} is its chord length (cm)
+ * inside pixel k.  Limits: 1 <= n <= 4096, 1 <= n_views, 1 <= n_bins,
+ * n_views * n_bins < 2^31, 0 < pixel_cm, sid_cm > n*pixel_cm/sqrt(2),
+ * sdd_cm > sid_cm. */
+typedef struct {
+  int32_t n;
+  double pixel_cm;
+  int32_t n_views, n_bins;
+  double sid_cm, sdd_cm, bin_cm;
+  double view0_rad, arc_rad;
+} osscir_geometry;
+
+/* Spectral tables of Eq. (fullModel), HOST pointers, copied at plan creation:
+ * mu [n_mat][n_energy] (cm^-1 per unit material fraction), s [n_win][n_energy]
+ * (each row >= 0 and summing to 1), n0 [n_win] incident photons per ray.
+ * Supported: n_mat = 3, n_win = 4, 1 <= n_energy <= 512. */
+typedef struct {
+  int32_t n_mat, n_win, n_energy;
+  const double *mu;
+  const double *s;
+  const double *n0;
+} osscir_spectral;
+
+/* Step-size ratio lambda > 0 (Sec. II: "a step size ratio parameter that must
+ * be tuned"), preconditioner and curvature choice, and whether the per-ray
+ * tail (3x3 eigen-clip, 4x4 dual solve) runs in FP64 (fp64_small = 1) or FP32
+ * (0).  Projection weights, line integrals and energy sums are FP32 in both
+ * cases; back-projection sums over views and the per-pixel 3x3 solve are
+ * always FP64 (the 3x3 step blocks are ill-conditioned). */
+typedef struct {
+  double lambda;
+  int32_t precond;
+  int32_t curvature;
+  int32_t fp64_small;
+} osscir_params;
+
+/* Iteration state, all DEVICE pointers owned by the caller.
+ *   f    [3][n][n]        f_n, updated in place to f_{n+1}
+ *   fbar [3][n][n]        extrapolated point fbar_n (the expansion point),
+ *                         updated in place to 2 f_{n+1} - f_n
+ *   y    [4][V][D]        dual variable, updated in place
+ *   c    [4][V][D]        measured counts (read only)
+ *   work, work_bytes      scratch of at least osscir_workspace_bytes() */
+typedef struct {
+  float *f;
+  float *fbar;
+  float *y;
+  const float *c;
+  void *work;
+  size_t work_bytes;
+} osscir_state;
+
+/* Build a plan: validates the inputs, allocates the device tables on the
+ * current device, builds the per-ray line parameters in FP64 and stores them
+ * as FP32, and computes rho_l = (X 1)_l with the library's own projector.
+ * Synchronises.  *out is set to NULL on failure. */
+int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec, osscir_plan *out);
+int osscir_plan_destroy(osscir_plan plan);
+
+/* Bytes of device scratch osscir_mocca_iterate, osscir_dtpl and the step
+ * calls need (host out-parameter). */
+int osscir_workspace_bytes(osscir_plan plan, size_t *bytes);
+
+/* rho_l = sum_k X_{l,k} (cm), the chord of each ray through the image square:
+ * copies the plan's [L] array into rho (device). */
+int osscir_ray_lengths(osscir_plan plan, float *rho, osscir_stream stream);
+
+/* Forward projection p_{c,l} = sum_k X_{l,k} f_{c,k} (Eq. fullModel's
+ * X f) of n_ch >= 1 channels: f [n_ch][n][n] -> p [n_ch][V][D].  Ray-driven;
+ * p is fully overwritten. */
+int osscir_forward_project(osscir_plan plan, const float *f, int32_t n_ch, float *p, osscir_stream stream);
+
+/* Back-projection b_{c,k} = sum_l X_{l,k} q_{c,l}, the exact transpose of
+ * osscir_forward_project (the same FP32 weight for every (ray, pixel) pair):
+ * q [n_ch][V][D] -> b [n_ch][n][n], fully overwritten; deterministic
+ * pixel-driven gather in fixed view order. */
+int osscir_back_project(osscir_plan plan, const float *q, int32_t n_ch, float *b, osscir_stream stream);
+
+/* Per-ray spectral model at material line integrals p [3][V][D] with counts
+ * c [4][V][D] (Sec. II): chat_{w,l} = N_w sum_i s_{w,i} softexp(-z_{l,i}),
+ * z = sum_m mu_{m,i} p_{m,l}; r = c - chat; G_l[w][m] = sum_i A_{wl,li} mu_{m,i}
+ * (so that K_{wl,mk} = G_l[w][m] X_{l,k}); H_l the p-space Hessian
+ * -mu diag(B^T r) mu^T + G^T diag(chat + r) G; and H_l^+ (negative
+ * eigenvalues set to zero).  Outputs (device, each may be NULL to skip):
+ * chat, r [4][L]; G [12][L] (index w*3+m); H, Hplus [6][L] (upper triangle
+ * 00,01,02,11,12,22).  fp64_small selects the precision of the eigen-clip. */
+int osscir_spectral_model(osscir_plan plan, const float *p, const float *c, float *chat, float *r, float *G,
+                          float *H, float *Hplus, int32_t fp64_small, osscir_stream stream);
+
+/* Block-diagonal SPC step lengths at G [12][L] (Sec. II):
+ *   sigma_{w,l} = 1 / (lambda sum_k sqrt(sum_m K^2)) = 1 / (lambda rho_l |G_l[w]|),
+ *   (T^-1)_k    = (1/lambda) sum_{w,l} K_{.,mk} K_{.,m'k} / |K_{.,k}|
+ *               = (1/lambda) sum_l X_{l,k} S_l,  S_l = sum_w G_l[w]^T G_l[w] / |G_l[w]|.
+ * Outputs: sigma [4][L] (0 for rays with rho_l = 0), tinv [6][n][n] (upper
+ * triangle of each 3x3 block).  Needs work. */
+int osscir_block_spc_steps(osscir_plan plan, const float *G, double lambda, float *sigma, float *tinv,
+                           void *work, size_t work_bytes, osscir_stream stream);
+
+/* Diagonal SPC step lengths (Sec. II):
+ *   sigma_{w,l} = (1/lambda) / sum_{mk} |K| = 1 / (lambda rho_l sum_m |G_l[w][m]|),
+ *   T_{mk}      = lambda / sum_{wl} |K|    = lambda / sum_l X_{l,k} sum_w |G_l[w][m]|.
+ * Outputs sigma [4][L], tau [3][n][n].  Needs work. */
+int osscir_diag_spc_steps(osscir_plan plan, const float *G, double lambda, float *sigma, float *tau, void *work,
+                          size_t work_bytes, osscir_stream stream);
+
+/* n_iter MOCCA iterations (CPPD steps on the local convex quadratic with
+ * expansion point fbar_n, one inner iteration per expansion point):
+ *   y_{n+1}    = prox_{Sigma Q*}(y_n + Sigma K fbar_n) = y_n + Sigma (Sigma + D_l)^-1 (r_l - y_n)
+ *   f_{n+1}    = f_n - T K^T y_{n+1}
+ *   fbar_{n+1} = 2 f_{n+1} - f_n
+ * with K, Sigma, T, r, D_l evaluated at fbar_n.  Rays with rho_l = 0 are
+ * masked (y = 0).  If dtpl is not NULL it is a DEVICE array of n_iter doubles
+ * receiving D_TPL(c, chat(f_{n+1})) after each iteration (an extra forward
+ * projection per iteration).  Two to three kernel launches per iteration,
+ * no host synchronisation. */
+int osscir_mocca_iterate(osscir_plan plan, const osscir_params *params, osscir_state *state, int32_t n_iter,
+                         double *dtpl, osscir_stream stream);
+
+/* D_TPL(c, chat(f)) of Eq. (DTPL) at maps f [3][n][n], accumulated in FP64
+ * in a fixed order, written to the DEVICE double *out.  Needs work. */
+int osscir_dtpl(osscir_plan plan, const float *f, const float *c, double *out, void *work, size_t work_bytes,
+                osscir_stream stream);
+
+/* Thread-local description of the last error ("" if none). */
+const char *osscir_last_error(void);
+
+/* Library version string. */
+const char *osscir_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OSSCIR_H */

@@ -1,0 +1,356 @@
+// The library's C ABI (include/osscir.h): plan construction on the host in
+// FP64, validation, workspace layout and the per-iteration launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "device_math.h"
+#include "kernels.h"
+#include "osscir.h"
+#include "projector.h"
+#include "spectral.h"
+
+using namespace osscir;
+
+struct osscir_plan_s {
+  int device = -1;
+  ScanDesc sd{};
+  RayLine *d_rays = nullptr;
+  float2 *d_views = nullptr;
+  float *d_rho = nullptr;
+  float *d_tab = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(OSSCIR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define OSSCIR_HIP(call, what)                   \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// workspace regions: p [3][L] f32 | qS [9][L] f32 | partial sums (f64)
+struct WorkLayout {
+  size_t p = 0, qS = 0, partial = 0, total = 0;
+};
+
+WorkLayout work_layout(const ScanDesc &sd) {
+  WorkLayout w;
+  const size_t L = (size_t)sd.n_rays;
+  w.p = 0;
+  w.qS = align256(w.p + 3 * L * sizeof(float));
+  w.partial = align256(w.qS + 9 * L * sizeof(float));
+  w.total = align256(w.partial + (size_t)dtpl_partial_count(sd) * sizeof(double));
+  return w;
+}
+
+int check_plan(osscir_plan plan) {
+  if (!plan) return fail(OSSCIR_EINVAL, "null plan");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
+    return fail(OSSCIR_EINVAL, "plan was created on device %d, current device is %d", plan->device, dev);
+  return OSSCIR_OK;
+}
+
+void free_plan(osscir_plan p) {
+  if (!p) return;
+  if (p->d_rays) (void)hipFree(p->d_rays);
+  if (p->d_views) (void)hipFree(p->d_views);
+  if (p->d_rho) (void)hipFree(p->d_rho);
+  if (p->d_tab) (void)hipFree(p->d_tab);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *osscir_last_error(void) { return g_last_error.c_str(); }
+
+const char *osscir_version(void) { return "osscir 0.1 gfx950"; }
+
+int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec, osscir_plan *out) {
+  g_last_error.clear();
+  if (!out) return fail(OSSCIR_EINVAL, "null output plan pointer");
+  *out = nullptr;
+  if (!geom || !spec) return fail(OSSCIR_EINVAL, "null geometry or spectral description");
+  const osscir_geometry g = *geom;
+  if (g.n < 1 || g.n > 4096) return fail(OSSCIR_EINVAL, "image size n=%d outside [1, 4096]", g.n);
+  if (g.n_views < 1 || g.n_bins < 1) return fail(OSSCIR_EINVAL, "need n_views >= 1 and n_bins >= 1");
+  if ((int64_t)g.n_views * g.n_bins >= ((int64_t)1 << 31) / 16)
+    return fail(OSSCIR_EINVAL, "too many rays (%d x %d)", g.n_views, g.n_bins);
+  if (!(g.pixel_cm > 0) || !(g.bin_cm > 0) || !std::isfinite(g.view0_rad) || !std::isfinite(g.arc_rad))
+    return fail(OSSCIR_EINVAL, "pixel_cm and bin_cm must be > 0, angles finite");
+  const double half_diag = g.n * g.pixel_cm / std::sqrt(2.0);
+  if (!(g.sid_cm > half_diag * 1.0001) || !(g.sdd_cm > g.sid_cm + half_diag * 1.0001))
+    return fail(OSSCIR_EINVAL, "source and detector must lie outside the image circumcircle");
+  if (spec->n_mat != kMat || spec->n_win != kWin)
+    return fail(OSSCIR_EINVAL, "supported: n_mat=3, n_win=4 (got %d, %d)", spec->n_mat, spec->n_win);
+  const int I = spec->n_energy;
+  if (I < 1 || I > 512) return fail(OSSCIR_EINVAL, "n_energy=%d outside [1, 512]", I);
+  if (!spec->mu || !spec->s || !spec->n0) return fail(OSSCIR_EINVAL, "null spectral table");
+  for (int w = 0; w < kWin; ++w) {
+    double sum = 0;
+    for (int i = 0; i < I; ++i) {
+      const double v = spec->s[w * I + i];
+      if (!(v >= 0) || !std::isfinite(v)) return fail(OSSCIR_EINVAL, "s[%d][%d] negative or not finite", w, i);
+      sum += v;
+    }
+    if (std::fabs(sum - 1.0) > 1e-6) return fail(OSSCIR_EINVAL, "row %d of s sums to %.9g, not 1", w, sum);
+    if (!(spec->n0[w] > 0) || !std::isfinite(spec->n0[w])) return fail(OSSCIR_EINVAL, "n0[%d] must be > 0", w);
+  }
+  for (int j = 0; j < kMat * I; ++j)
+    if (!std::isfinite(spec->mu[j])) return fail(OSSCIR_EINVAL, "mu not finite");
+
+  osscir_plan p = new (std::nothrow) osscir_plan_s;
+  if (!p) return fail(OSSCIR_ENOMEM, "host allocation failed");
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(OSSCIR_EDEVICE, "no HIP device");
+  }
+  const int V = g.n_views, D = g.n_bins, N = g.n;
+  const size_t L = (size_t)V * D;
+  const double h = g.pixel_cm;
+
+  // per-ray line parameters (pixel units): normal and offset kept in FP64,
+  // the trapezoid constants rounded to FP32
+  std::vector<RayLine> rays(L);
+  std::vector<float2> views(V);
+  for (int v = 0; v < V; ++v) {
+    const double beta = g.view0_rad + g.arc_rad * (double)v / (double)V;
+    const double cb = std::cos(beta), sb = std::sin(beta);
+    views[v] = make_float2((float)cb, (float)sb);
+    const double sx = g.sid_cm * cb / h, sy = g.sid_cm * sb / h;
+    for (int d = 0; d < D; ++d) {
+      const double u = ((double)d - 0.5 * (D - 1)) * g.bin_cm;
+      const double px = (-(g.sdd_cm - g.sid_cm) * cb - u * sb) / h;
+      const double py = (-(g.sdd_cm - g.sid_cm) * sb + u * cb) / h;
+      double tx = px - sx, ty = py - sy;
+      const double len = std::sqrt(tx * tx + ty * ty);
+      tx /= len;
+      ty /= len;
+      const double nx = -ty, ny = tx;
+      const double s = nx * sx + ny * sy;
+      const double anx = std::fabs(nx), any = std::fabs(ny);
+      const double a = 0.5 * (anx + any);
+      const double hmax = h / std::max(anx, any);
+      const double prod = anx * any;
+      const double kappa = (prod * 1e30 > h) ? h / prod : 1e30;
+      const size_t l = (size_t)v * D + d;
+      rays[l] = RayLine{nx, ny, s, (float)a, (float)hmax, (float)kappa, 0.0f};
+    }
+  }
+  // spectral table
+  std::vector<float> tab((size_t)I * kTab, 0.0f);
+  for (int i = 0; i < I; ++i) {
+    float *t = &tab[(size_t)i * kTab];
+    const double mu[3] = {spec->mu[0 * I + i], spec->mu[1 * I + i], spec->mu[2 * I + i]};
+    for (int m = 0; m < 3; ++m) t[kTabMu + m] = (float)mu[m];
+    for (int w = 0; w < kWin; ++w) {
+      const double s = spec->s[w * I + i];
+      t[kTabS + w] = (float)s;
+      for (int m = 0; m < 3; ++m) t[kTabSMu + 3 * w + m] = (float)(s * mu[m]);
+      int k = 0;
+      for (int m = 0; m < 3; ++m)
+        for (int n = m; n < 3; ++n) t[kTabSMuMu + 6 * w + (k++)] = (float)(s * mu[m] * mu[n]);
+    }
+  }
+
+  hipError_t e;
+  if ((e = hipMalloc(&p->d_rays, rays.size() * sizeof(RayLine))) != hipSuccess ||
+      (e = hipMalloc(&p->d_views, views.size() * sizeof(float2))) != hipSuccess ||
+      (e = hipMalloc(&p->d_rho, L * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc(&p->d_tab, tab.size() * sizeof(float))) != hipSuccess) {
+    free_plan(p);
+    return fail(OSSCIR_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  if ((e = hipMemcpy(p->d_rays, rays.data(), rays.size() * sizeof(RayLine), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->d_views, views.data(), views.size() * sizeof(float2), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(p->d_tab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "copying plan tables");
+  }
+  ScanDesc &sd = p->sd;
+  sd.n = N;
+  sd.n_views = V;
+  sd.n_bins = D;
+  sd.n_rays = (int)L;
+  sd.n_energy = I;
+  sd.c0 = 0.5f * (float)(N - 1);
+  sd.c0d = 0.5 * (double)(N - 1);
+  sd.sid_px = (float)(g.sid_cm / h);
+  sd.bin_scale = (float)(g.sdd_cm / g.bin_cm);
+  sd.cbin = 0.5f * (float)(D - 1);
+  for (int w = 0; w < kWin; ++w) sd.n0[w] = (float)spec->n0[w];
+  sd.rays = p->d_rays;
+  sd.views = p->d_views;
+  sd.rho = p->d_rho;
+  sd.tab = p->d_tab;
+
+  // rho = X 1 with the library's own projector
+  float *ones = nullptr;
+  if ((e = hipMalloc(&ones, (size_t)N * N * sizeof(float))) != hipSuccess) {
+    free_plan(p);
+    return fail(OSSCIR_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  std::vector<float> h_ones((size_t)N * N, 1.0f);
+  e = hipMemcpy(ones, h_ones.data(), h_ones.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_forward(sd, ones, 1, p->d_rho, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  (void)hipFree(ones);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "computing ray lengths");
+  }
+  *out = p;
+  return OSSCIR_OK;
+}
+
+int osscir_plan_destroy(osscir_plan plan) {
+  if (!plan) return OSSCIR_OK;
+  (void)hipDeviceSynchronize();
+  free_plan(plan);
+  return OSSCIR_OK;
+}
+
+int osscir_workspace_bytes(osscir_plan plan, size_t *bytes) {
+  if (!plan || !bytes) return fail(OSSCIR_EINVAL, "null argument");
+  *bytes = work_layout(plan->sd).total;
+  return OSSCIR_OK;
+}
+
+int osscir_ray_lengths(osscir_plan plan, float *rho, osscir_stream stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!rho) return fail(OSSCIR_EINVAL, "null rho");
+  OSSCIR_HIP(hipMemcpyAsync(rho, plan->d_rho, (size_t)plan->sd.n_rays * sizeof(float), hipMemcpyDeviceToDevice,
+                            (hipStream_t)stream),
+             "copying rho");
+  return OSSCIR_OK;
+}
+
+int osscir_forward_project(osscir_plan plan, const float *f, int32_t n_ch, float *p, osscir_stream stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!f || !p || n_ch < 1) return fail(OSSCIR_EINVAL, "forward_project: null pointer or n_ch < 1");
+  OSSCIR_HIP(launch_forward(plan->sd, f, n_ch, p, (hipStream_t)stream), "forward_project launch");
+  return OSSCIR_OK;
+}
+
+int osscir_back_project(osscir_plan plan, const float *q, int32_t n_ch, float *b, osscir_stream stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!q || !b || n_ch < 1) return fail(OSSCIR_EINVAL, "back_project: null pointer or n_ch < 1");
+  OSSCIR_HIP(launch_back(plan->sd, q, n_ch, b, (hipStream_t)stream), "back_project launch");
+  return OSSCIR_OK;
+}
+
+int osscir_spectral_model(osscir_plan plan, const float *p, const float *c, float *chat, float *r, float *G,
+                          float *H, float *Hplus, int32_t fp64_small, osscir_stream stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!p || !c) return fail(OSSCIR_EINVAL, "spectral_model: null p or c");
+  OSSCIR_HIP(launch_spectral_model(plan->sd, p, c, chat, r, G, H, Hplus, fp64_small != 0, (hipStream_t)stream),
+             "spectral_model launch");
+  return OSSCIR_OK;
+}
+
+static int steps_common(osscir_plan plan, const float *G, double lambda, float *sigma, float *img, void *work,
+                        size_t work_bytes, bool block, osscir_stream stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!G || !sigma || !img || !work) return fail(OSSCIR_EINVAL, "spc_steps: null pointer");
+  if (!(lambda > 0) || !std::isfinite(lambda)) return fail(OSSCIR_EINVAL, "lambda must be > 0");
+  const WorkLayout wl = work_layout(plan->sd);
+  if (work_bytes < wl.total) return fail(OSSCIR_ESTATE, "workspace %zu < %zu bytes", work_bytes, wl.total);
+  float *terms = (float *)((char *)work + wl.qS);
+  OSSCIR_HIP(launch_steps(plan->sd, G, (float)lambda, block, sigma, terms, img, (hipStream_t)stream),
+             "spc_steps launch");
+  return OSSCIR_OK;
+}
+
+int osscir_block_spc_steps(osscir_plan plan, const float *G, double lambda, float *sigma, float *tinv, void *work,
+                           size_t work_bytes, osscir_stream stream) {
+  return steps_common(plan, G, lambda, sigma, tinv, work, work_bytes, true, stream);
+}
+
+int osscir_diag_spc_steps(osscir_plan plan, const float *G, double lambda, float *sigma, float *tau, void *work,
+                          size_t work_bytes, osscir_stream stream) {
+  return steps_common(plan, G, lambda, sigma, tau, work, work_bytes, false, stream);
+}
+
+int osscir_mocca_iterate(osscir_plan plan, const osscir_params *params, osscir_state *state, int32_t n_iter,
+                         double *dtpl, osscir_stream stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!params || !state) return fail(OSSCIR_EINVAL, "mocca_iterate: null params or state");
+  if (n_iter < 0) return fail(OSSCIR_EINVAL, "n_iter < 0");
+  if (!state->f || !state->fbar || !state->y || !state->c || !state->work)
+    return fail(OSSCIR_EINVAL, "mocca_iterate: null state buffer");
+  if (!(params->lambda > 0) || !std::isfinite(params->lambda)) return fail(OSSCIR_EINVAL, "lambda must be > 0");
+  if (params->precond != OSSCIR_PRECOND_DIAG && params->precond != OSSCIR_PRECOND_BLOCK)
+    return fail(OSSCIR_EINVAL, "unknown preconditioner %d", params->precond);
+  if (params->curvature != OSSCIR_CURV_WINDOW && params->curvature != OSSCIR_CURV_CLIP)
+    return fail(OSSCIR_EINVAL, "unknown curvature %d", params->curvature);
+  const WorkLayout wl = work_layout(plan->sd);
+  if (state->work_bytes < wl.total)
+    return fail(OSSCIR_ESTATE, "workspace %zu < %zu bytes", state->work_bytes, wl.total);
+  const ScanDesc &sd = plan->sd;
+  hipStream_t st = (hipStream_t)stream;
+  float *p = (float *)((char *)state->work + wl.p);
+  float *qS = (float *)((char *)state->work + wl.qS);
+  double *partial = (double *)((char *)state->work + wl.partial);
+  const bool block = params->precond == OSSCIR_PRECOND_BLOCK;
+  const bool clip = params->curvature == OSSCIR_CURV_CLIP;
+  const bool fp64 = params->fp64_small != 0;
+  const float lam = (float)params->lambda;
+  for (int it = 0; it < n_iter; ++it) {
+    OSSCIR_HIP(launch_forward(sd, state->fbar, 3, p, st), "mocca: forward projection");
+    OSSCIR_HIP(launch_spectral_dual(sd, p, state->c, state->y, qS, lam, clip, block, fp64, st),
+               "mocca: spectral model and dual step");
+    OSSCIR_HIP(launch_back_primal(sd, qS, state->f, state->fbar, lam, block, fp64, st),
+               "mocca: back-projection and primal step");
+    if (dtpl) OSSCIR_HIP(launch_dtpl(sd, state->f, state->c, p, partial, dtpl + it, st), "mocca: D_TPL");
+  }
+  return OSSCIR_OK;
+}
+
+int osscir_dtpl(osscir_plan plan, const float *f, const float *c, double *out, void *work, size_t work_bytes,
+                osscir_stream stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!f || !c || !out || !work) return fail(OSSCIR_EINVAL, "dtpl: null pointer");
+  const WorkLayout wl = work_layout(plan->sd);
+  if (work_bytes < wl.total) return fail(OSSCIR_ESTATE, "workspace %zu < %zu bytes", work_bytes, wl.total);
+  float *p = (float *)((char *)work + wl.p);
+  double *partial = (double *)((char *)work + wl.partial);
+  OSSCIR_HIP(launch_dtpl(plan->sd, f, c, p, partial, out, (hipStream_t)stream), "dtpl launch");
+  return OSSCIR_OK;
+}
+
+}  // extern "C"

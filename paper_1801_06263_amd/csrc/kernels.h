@@ -1,0 +1,45 @@
+// Kernel-side data layouts and launch helpers shared by the library's
+// translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace osscir {
+
+struct RayLine;
+
+constexpr int kMat = 3;   // materials (block SPC works on 3x3 blocks)
+constexpr int kWin = 4;   // energy windows
+constexpr int kTab = 48;  // floats per energy in the spectral table
+
+// Spectral table, one row of kTab floats per energy i:
+//   [0..2]   mu_{m,i}
+//   [3..6]   s_{w,i}
+//   [7..18]  s_{w,i} mu_{m,i}                  (index 7 + 3w + m)
+//   [19..42] s_{w,i} mu_{m,i} mu_{n,i}, m <= n (index 19 + 6w + upper(m,n))
+//   [43..47] zero
+constexpr int kTabMu = 0, kTabS = 3, kTabSMu = 7, kTabSMuMu = 19;
+
+// Everything a kernel needs to know about one scan.
+struct ScanDesc {
+  int n;             // image side
+  int n_views;
+  int n_bins;
+  int n_rays;        // n_views * n_bins
+  int n_energy;
+  float c0;          // (n - 1) / 2
+  double c0d;        // (n - 1) / 2
+  float sid_px;      // source-isocentre distance, pixel units
+  float bin_scale;   // sdd / bin pitch (bins per unit tan)
+  float cbin;        // (n_bins - 1) / 2
+  float n0[kWin];    // incident counts per window
+  const struct RayLine *rays;  // [L]
+  const float2 *views;  // [V] (cos beta, sin beta)
+  const float *rho;     // [L]
+  const float *tab;     // [I][kTab]
+};
+
+}  // namespace osscir

@@ -1,0 +1,29 @@
+// Launchers of the per-ray spectral kernels, the fused primal update and
+// the D_TPL reduction (spectral.hip).
+#pragma once
+
+#include "kernels.h"
+
+namespace osscir {
+
+hipError_t launch_spectral_model(const ScanDesc &sd, const float *p, const float *c, float *chat, float *r,
+                                 float *G, float *H, float *Hp, bool fp64, hipStream_t st);
+
+// y, qS updated from p (line integrals at the expansion point) and counts c.
+hipError_t launch_spectral_dual(const ScanDesc &sd, const float *p, const float *c, float *y, float *qS,
+                                float lambda, bool clip, bool block, bool fp64, hipStream_t st);
+
+// back-projection of qS fused with the primal step and the extrapolation.
+hipError_t launch_back_primal(const ScanDesc &sd, const float *qS, float *f, float *fbar, float lambda, bool block,
+                              bool fp64, hipStream_t st);
+
+// sigma [4][L], per-ray terms (scratch, 6 or 3 channels) and the pixel
+// steps out_img (T^-1 upper triangles or tau).
+hipError_t launch_steps(const ScanDesc &sd, const float *G, float lambda, bool block, float *sigma, float *terms,
+                        float *out_img, hipStream_t st);
+
+int dtpl_partial_count(const ScanDesc &sd);
+hipError_t launch_dtpl(const ScanDesc &sd, const float *f, const float *c, float *p_scratch, double *partial,
+                       double *out, hipStream_t st);
+
+}  // namespace osscir

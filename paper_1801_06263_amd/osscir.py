@@ -1,0 +1,269 @@
+"""Thin ctypes binding of libosscir (include/osscir.h).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+library.  PyTorch supplies device memory and the current stream.  If the
+shared library has not been built this module raises on first use; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libosscir.so")
+
+PRECOND_DIAG, PRECOND_BLOCK = 0, 1
+CURV_WINDOW, CURV_CLIP = 0, 1
+
+c_int32, c_double, c_size_t, c_void_p = ctypes.c_int32, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class _Geometry(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("pixel_cm", c_double), ("n_views", c_int32), ("n_bins", c_int32),
+                ("sid_cm", c_double), ("sdd_cm", c_double), ("bin_cm", c_double),
+                ("view0_rad", c_double), ("arc_rad", c_double)]
+
+
+class _Spectral(ctypes.Structure):
+    _fields_ = [("n_mat", c_int32), ("n_win", c_int32), ("n_energy", c_int32),
+                ("mu", _dp), ("s", _dp), ("n0", _dp)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("lam", c_double), ("precond", c_int32), ("curvature", c_int32), ("fp64_small", c_int32)]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("f", c_void_p), ("fbar", c_void_p), ("y", c_void_p), ("c", c_void_p),
+                ("work", c_void_p), ("work_bytes", c_size_t)]
+
+
+# name -> (restype, argtypes) for every entry point of include/osscir.h
+SIGNATURES = {
+    "osscir_plan_create": (c_int32, [ctypes.POINTER(_Geometry), ctypes.POINTER(_Spectral), ctypes.POINTER(c_void_p)]),
+    "osscir_plan_destroy": (c_int32, [c_void_p]),
+    "osscir_workspace_bytes": (c_int32, [c_void_p, ctypes.POINTER(c_size_t)]),
+    "osscir_ray_lengths": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "osscir_forward_project": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "osscir_back_project": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "osscir_spectral_model": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_int32, c_void_p]),
+    "osscir_block_spc_steps": (c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_size_t,
+                                         c_void_p]),
+    "osscir_diag_spc_steps": (c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_size_t,
+                                        c_void_p]),
+    "osscir_mocca_iterate": (c_int32, [c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_State), c_int32, c_void_p,
+                                       c_void_p]),
+    "osscir_dtpl": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "osscir_last_error": (ctypes.c_char_p, []),
+    "osscir_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libosscir.so and declare its signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libosscir.so not built at {path}: run `python -m paper_1801_06263_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class OsscirError(RuntimeError):
+    pass
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = _lib.osscir_last_error().decode(errors="replace")
+        raise OsscirError(f"osscir error {rc}: {msg}")
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return c_void_p(s.cuda_stream)
+
+
+def _dev(t, shape=None, dtype=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class Params:
+    lam: float
+    precond: str = "block"       # "block" | "diag"
+    curvature: str = "clip"      # "clip" | "window"
+    fp64_small: bool = False
+
+    def to_c(self) -> _Params:
+        pre = {"diag": PRECOND_DIAG, "block": PRECOND_BLOCK}[self.precond]
+        cur = {"window": CURV_WINDOW, "clip": CURV_CLIP}[self.curvature]
+        return _Params(float(self.lam), pre, cur, int(bool(self.fp64_small)))
+
+
+@dataclasses.dataclass
+class State:
+    """Device-resident iteration state (torch CUDA tensors)."""
+    f: "object"      # [3, n, n] f32
+    fbar: "object"   # [3, n, n] f32
+    y: "object"      # [4, V, D] f32
+    c: "object"      # [4, V, D] f32
+    work: "object"   # [workspace_bytes] u8
+
+
+class Plan:
+    """A scan (geometry + spectral tables) prepared on the current device."""
+
+    def __init__(self, geom, spec):
+        lib = load_library()
+        self.n, self.n_views, self.n_bins = int(geom.n), int(geom.n_views), int(geom.n_bins)
+        g = _Geometry(self.n, float(geom.pixel_cm), self.n_views, self.n_bins, float(geom.sid_cm),
+                      float(geom.sdd_cm), float(geom.bin_cm), float(getattr(geom, "view0_rad", 0.0)),
+                      float(getattr(geom, "arc_rad", 2 * np.pi)))
+        self._mu = np.ascontiguousarray(spec.mu, dtype=np.float64)
+        self._s = np.ascontiguousarray(spec.s, dtype=np.float64)
+        self._n0 = np.ascontiguousarray(spec.n0, dtype=np.float64)
+        sp = _Spectral(self._mu.shape[0], self._s.shape[0], self._s.shape[1],
+                       self._mu.ctypes.data_as(_dp), self._s.ctypes.data_as(_dp), self._n0.ctypes.data_as(_dp))
+        h = c_void_p()
+        _check(lib.osscir_plan_create(ctypes.byref(g), ctypes.byref(sp), ctypes.byref(h)))
+        self._h = h
+        nb = c_size_t()
+        _check(lib.osscir_workspace_bytes(self._h, ctypes.byref(nb)))
+        self.workspace_bytes = int(nb.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(_lib.osscir_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- shapes
+    @property
+    def sino_shape(self):
+        return (self.n_views, self.n_bins)
+
+    @property
+    def img_shape(self):
+        return (self.n, self.n)
+
+    def _empty(self, *shape, dtype=None):
+        import torch
+        return torch.empty(*shape, dtype=dtype or torch.float32, device="cuda")
+
+    def workspace(self):
+        import torch
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
+
+    # -- entry points
+    def ray_lengths(self, stream=None):
+        out = self._empty(*self.sino_shape)
+        _check(_lib.osscir_ray_lengths(self._h, _dev(out), _stream_handle(stream)))
+        return out
+
+    def forward_project(self, f, out=None, stream=None):
+        import torch
+        nch = f.shape[0]
+        fp = _dev(f, (nch, self.n, self.n), torch.float32, "f")
+        out = self._empty(nch, *self.sino_shape) if out is None else out
+        _check(_lib.osscir_forward_project(self._h, fp, nch, _dev(out, (nch, *self.sino_shape), torch.float32, "p"),
+                                           _stream_handle(stream)))
+        return out
+
+    def back_project(self, q, out=None, stream=None):
+        import torch
+        nch = q.shape[0]
+        qp = _dev(q, (nch, *self.sino_shape), torch.float32, "q")
+        out = self._empty(nch, self.n, self.n) if out is None else out
+        _check(_lib.osscir_back_project(self._h, qp, nch, _dev(out, (nch, self.n, self.n), torch.float32, "b"),
+                                        _stream_handle(stream)))
+        return out
+
+    def spectral_model(self, p, c, fp64_small=False, stream=None):
+        import torch
+        V, D = self.sino_shape
+        out = {"chat": self._empty(4, V, D), "r": self._empty(4, V, D), "G": self._empty(12, V, D),
+               "H": self._empty(6, V, D), "Hplus": self._empty(6, V, D)}
+        _check(_lib.osscir_spectral_model(
+            self._h, _dev(p, (3, V, D), torch.float32, "p"), _dev(c, (4, V, D), torch.float32, "c"),
+            _dev(out["chat"]), _dev(out["r"]), _dev(out["G"]), _dev(out["H"]), _dev(out["Hplus"]),
+            int(bool(fp64_small)), _stream_handle(stream)))
+        return out
+
+    def spc_steps(self, G, lam, precond="block", work=None, stream=None):
+        import torch
+        V, D = self.sino_shape
+        work = self.workspace() if work is None else work
+        sigma = self._empty(4, V, D)
+        img = self._empty(6 if precond == "block" else 3, self.n, self.n)
+        fn = _lib.osscir_block_spc_steps if precond == "block" else _lib.osscir_diag_spc_steps
+        _check(fn(self._h, _dev(G, (12, V, D), torch.float32, "G"), float(lam), _dev(sigma), _dev(img),
+                  _dev(work), work.numel(), _stream_handle(stream)))
+        return sigma, img
+
+    def new_state(self, c, f0=None):
+        """Device state for MOCCA from counts c [4, V, D] (f0 = fbar0 = f0 or 0, y0 = 0)."""
+        import torch
+        f = torch.zeros(3, self.n, self.n, dtype=torch.float32, device="cuda") if f0 is None \
+            else f0.to(device="cuda", dtype=torch.float32).contiguous().clone()
+        return State(f=f, fbar=f.clone(), y=torch.zeros(4, *self.sino_shape, dtype=torch.float32, device="cuda"),
+                     c=c.to(device="cuda", dtype=torch.float32).contiguous(), work=self.workspace())
+
+    def mocca_iterate(self, state: State, params: Params, n_iter: int, dtpl: bool = False, stream=None):
+        """Run n_iter iterations in place; returns a [n_iter] float64 device tensor of D_TPL if asked."""
+        import torch
+        V, D = self.sino_shape
+        st = _State(_dev(state.f, (3, self.n, self.n), torch.float32, "f").value,
+                    _dev(state.fbar, (3, self.n, self.n), torch.float32, "fbar").value,
+                    _dev(state.y, (4, V, D), torch.float32, "y").value,
+                    _dev(state.c, (4, V, D), torch.float32, "c").value,
+                    _dev(state.work, None, torch.uint8, "work").value, state.work.numel())
+        out = torch.empty(max(n_iter, 1), dtype=torch.float64, device="cuda") if dtpl else None
+        prm = params.to_c()
+        _check(_lib.osscir_mocca_iterate(self._h, ctypes.byref(prm), ctypes.byref(st), int(n_iter),
+                                         _dev(out) if dtpl else None, _stream_handle(stream)))
+        return out
+
+    def dtpl(self, f, c, work=None, stream=None):
+        """D_TPL(c, chat(f)) as a 0-d float64 device tensor."""
+        import torch
+        work = self.workspace() if work is None else work
+        out = torch.empty((), dtype=torch.float64, device="cuda")
+        _check(_lib.osscir_dtpl(self._h, _dev(f, (3, self.n, self.n), torch.float32, "f"),
+                                _dev(c, (4, *self.sino_shape), torch.float32, "c"), _dev(out), _dev(work),
+                                work.numel(), _stream_handle(stream)))
+        return out
+
+
+def version() -> str:
+    return load_library().osscir_version().decode()
