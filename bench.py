@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""MOCCA iterations per second for one-step three-material spectral CT on one
+MI355X: 512^2 material maps, 720 views x 1024 bins fan beam, 120 energy bins,
+four overlapping windows, block-diagonal SPC, clipped curvature (the "large"
+workload of synth.problem).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+One step = one MOCCA iteration (forward projection of fbar, per-ray spectral
+model + step lengths + dual step, back-projection fused with the primal step),
+with every input resident on the device.  Prints one JSON line with the
+iteration rate, the projector rates, a roofline entry for the dominant kernel
+(its average duration measured here with events on the library's stream) and
+the FP64 oracle timed on the host as a CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MOCCA iter/s + projector GRays/s at 512^2 x4 windows; batched solves/s; p50/p99"
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz of non-packed VALU issue; HBM3E 8 TB/s.
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic work per unit (lane operations, an FMA counts one):
+#   chord weight of one (ray, pixel) pair: 2 FMA (signed distance) + |.|-sub,
+#     mul, max, min = 6; forward projection adds 3 FMA, back-projection 9.
+#   one (ray, energy) pair of the energy loop: z 3, exp 2, softexp selects 3,
+#     window sums 4, Jacobian rows 12, curvature sums 24 (clip) -> 48; window
+#     curvature drops the 24 and one select -> 23.
+#   per-ray tail: step lengths, Hessian, eigen-clip, 4x4 dual solve ~ 400
+#     (clip) / 60 (window); per-pixel 3x3 equilibrated solve + update ~ 60.
+OPS = {"w": 6, "fp_fma": 3, "bp_fma_block": 9, "bp_fma_diag": 6, "energy_clip": 48, "energy_window": 23,
+       "tail_clip": 400, "tail_window": 60, "pixel": 60}
+# Algorithmic HBM bytes per iteration (FP32): per ray c 4 + y in/out 8 + rho 1
+# + p write/read 6 + qS write/read 18 words; per pixel f, fbar read and written 12.
+BYTES_PER_RAY = 4 * 37
+BYTES_PER_PIXEL = 4 * 12
+
+KERNEL_NAMES = {0: "k_forward<3>", 1: "k_spectral_dual", 2: "k_back_primal"}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="large", choices=["tiny", "medium", "large"])
+    ap.add_argument("--precond", default="block", choices=["block", "diag"])
+    ap.add_argument("--curvature", default="clip", choices=["clip", "window"])
+    ap.add_argument("--fp64-small", type=int, default=0)
+    ap.add_argument("--lam", type=float, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-views", default="12,36", help="view-subset sizes of the oracle sample")
+    ap.add_argument("--json-out", default=None)
+    return ap.parse_args()
+
+
+DEFAULT_LAM = {"tiny": 3e-7, "medium": 2e-7, "large": 4e-8}
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1801_06263_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(workload, {}).get(kernel)
+    if not ent or ent.get("source_hash") != source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(pr, lam, precond, curvature, view_counts):
+    """The FP64 oracle's MOCCA iteration timed on host cores over view subsets
+    of the same scan; the per-iteration time is extrapolated linearly in the
+    number of views (fixed per-pixel cost + per-ray cost)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import model, mocca, projector
+
+    times = []
+    with threadpool_limits(limits=1):
+        for nv in view_counts:
+            views = np.linspace(0, pr.geom.n_views, nv, endpoint=False).astype(int)
+            X = projector.system_matrix(pr.geom, views=views)
+            chat = model.counts_model(X @ pr.f_true.reshape(3, -1).T, pr.spec)
+            c = synth.poisson_counts(chat, pr.seed)
+            rho = np.asarray(X.sum(axis=1)).ravel()
+            st = mocca.initial_state(3, X.shape[1], X.shape[0], 4)
+            st = mocca.mocca_step(X, rho, st, c, pr.spec, lam, precond, curvature)
+            t0 = time.perf_counter()
+            reps = 2
+            for _ in range(reps):
+                st = mocca.mocca_step(X, rho, st, c, pr.spec, lam, precond, curvature)
+            times.append((nv, (time.perf_counter() - t0) / reps))
+    (v0, t0), (v1, t1) = times[0], times[-1]
+    slope = (t1 - t0) / (v1 - v0)
+    t_full = t0 + slope * (pr.geom.n_views - v0)
+    sample = (f"{'+'.join(str(v) for v, _ in times)}-view subsets of the {pr.geom.n_views}-view scan, "
+              f"{'/'.join(f'{t:.2f}' for _, t in times)} s per iteration, linear in views -> "
+              f"{t_full:.1f} s per full iteration")
+    return {"value": 1.0 / t_full, "unit": "iter/s", "cores": 1, "kind": "oracle", "sample": sample}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: multi-GPU runs are not part of this build "
+              "(slices shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1801_06263_amd import Params, Plan
+
+    torch.cuda.set_device(0)
+    pr = synth.problem(args.workload)
+    geom = pr.geom
+    lam = args.lam if args.lam is not None else DEFAULT_LAM[args.workload]
+    t_setup = time.perf_counter()
+    plan = Plan(geom, pr.spec)
+    V, D, N = geom.n_views, geom.n_bins, geom.n
+    L = V * D
+    # synthetic measured counts from the library's own counts model at the phantom
+    f_true = torch.as_tensor(pr.f_true.astype(np.float32)).cuda()
+    p_true = plan.forward_project(f_true)
+    chat = plan.spectral_model(p_true, torch.zeros(4, V, D, device="cuda"))["chat"]
+    c = synth.poisson_counts(chat.double().cpu().numpy(), pr.seed).astype(np.float32)
+    state = plan.new_state(torch.from_numpy(c).cuda())
+    params = Params(lam, args.precond, args.curvature, bool(args.fp64_small))
+    nnz = int(plan.ray_nnz().sum().item())
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    print(f"[bench] {args.workload}: {N}^2, {V}x{D} rays, {pr.spec.n_energy} energies, nnz(X)={nnz}, "
+          f"setup {t_setup:.1f}s; warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
+
+    # warmup, then the timed region: K whole iterations
+    plan.mocca_iterate(state, params, args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record()
+    plan.mocca_iterate(state, params, args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_total = e0.elapsed_time(e1)
+    ms_per_step = ms_total / args.steps
+    finite = bool(torch.isfinite(state.f).all().item() and torch.isfinite(state.y).all().item())
+    print(f"[bench] {ms_per_step:.3f} ms/iteration ({t_wall:.2f}s wall for {args.steps}), state finite={finite}",
+          file=sys.stderr, flush=True)
+
+    # per-kernel durations: the same iterations stage by stage, events on the library's stream
+    stage_ms = [0.0, 0.0, 0.0]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(args.steps):
+        ev[0].record()
+        for s in range(3):
+            plan.mocca_stage(state, params, s)
+            ev[s + 1].record()
+        torch.cuda.synchronize()
+        for s in range(3):
+            stage_ms[s] += ev[s].elapsed_time(ev[s + 1])
+    stage_ms = [t / args.steps for t in stage_ms]
+
+    # projector rates: 3-channel forward projection, 9-channel back-projection
+    q9 = torch.randn(9, V, D, device="cuda")
+    fp_out = torch.empty(3, V, D, device="cuda")
+    bp_out = torch.empty(9, N, N, device="cuda")
+    plan.forward_project(state.fbar, out=fp_out)
+    plan.back_project(q9, out=bp_out)
+    a0, a1, a2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    a0.record()
+    for _ in range(args.steps):
+        plan.forward_project(state.fbar, out=fp_out)
+    a1.record()
+    for _ in range(args.steps):
+        plan.back_project(q9, out=bp_out)
+    a2.record()
+    torch.cuda.synchronize()
+    fp_ms = a0.elapsed_time(a1) / args.steps
+    bp_ms = a1.elapsed_time(a2) / args.steps
+
+    # roofline of the dominant kernel
+    I = pr.spec.n_energy
+    clip = args.curvature == "clip"
+    ops = [
+        (OPS["w"] + OPS["fp_fma"]) * nnz,
+        (OPS["energy_clip" if clip else "energy_window"] * I + OPS["tail_clip" if clip else "tail_window"]) * L,
+        (OPS["w"] + (OPS["bp_fma_block"] if args.precond == "block" else OPS["bp_fma_diag"])) * nnz
+        + OPS["pixel"] * N * N,
+    ]
+    dom = max(range(3), key=lambda s: stage_ms[s])
+    achieved = ops[dom] / (stage_ms[dom] * 1e-3) / 1e12
+    traffic = measured_traffic(KERNEL_NAMES[dom], args.workload)
+    hbm_bytes = BYTES_PER_RAY * L + BYTES_PER_PIXEL * N * N
+    line = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms_per_step, 3),
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {N}^2 maps x3 materials, fan beam {V} views x {D} bins, "
+                               f"{I} energies, 4 overlapping windows",
+                   "precond": args.precond, "curvature": args.curvature, "lambda": lam,
+                   "fp64_small": bool(args.fp64_small), "nnz_X": nnz},
+        "projector": {"fp_grays_s": round(L / (fp_ms * 1e-3) / 1e9, 3), "fp_ms_3ch": round(fp_ms, 4),
+                      "bp_grays_s": round(L / (bp_ms * 1e-3) / 1e9, 3), "bp_ms_9ch": round(bp_ms, 4)},
+        "stages_ms": {KERNEL_NAMES[s]: round(stage_ms[s], 4) for s in range(3)},
+        "roofline": {"bound": "alu", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 3),
+                     "peak": round(PEAK_VALU_TOPS, 2), "unit": "Top/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
+                     "traffic": traffic},
+        "hbm": {"algorithmic_bytes_per_step": hbm_bytes,
+                "achieved_gbs": round(hbm_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+                "frac": round(hbm_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 5)},
+        "state_finite": finite,
+    }
+    if not args.no_cpu_baseline:
+        views = [int(v) for v in args.cpu_views.split(",")]
+        print(f"[bench] cpu baseline: oracle on {views}-view subsets", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(pr, lam, args.precond, args.curvature, views)
+    out = json.dumps(line)
+    print(out, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as fh:
+            fh.write(out + "\n")
+
+
+if __name__ == "__main__":
+    main()

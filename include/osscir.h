@@ -17,9 +17,10 @@
  *  - Every data pointer argument is a DEVICE pointer owned by the caller
  *    (allocated on the device the plan was created on), unless documented
  *    "host".  The library allocates device memory only inside
- *    osscir_plan_create (its constant tables and ray geometry) and frees it
- *    in osscir_plan_destroy; it keeps no pointer to caller memory after a
- *    call returns.
+ *    osscir_plan_create (its constant tables, ray geometry and a 32 n^2-byte
+ *    image scratch used by osscir_forward_project) and frees it in
+ *    osscir_plan_destroy; it keeps no pointer to caller memory after a call
+ *    returns.
  *  - Calls that take a stream enqueue their work asynchronously on it (NULL =
  *    the null stream) and return without synchronising.  Only
  *    osscir_plan_create and osscir_plan_destroy synchronise.
@@ -27,8 +28,9 @@
  *    unsupported material/window count), OSSCIR_EDEVICE (-2: a HIP call or
  *    launch failed), OSSCIR_ENOMEM (-3), OSSCIR_ESTATE (-4: workspace too
  *    small).  osscir_last_error() returns the calling thread's last message.
- *  - A plan may be used from one host thread at a time; different plans are
- *    independent.  Results are deterministic: no floating-point atomics, fixed
+ *  - A plan may be used from one host thread and one stream at a time
+ *    (osscir_forward_project uses the plan's scratch; the iteration calls use
+ *    the caller's workspace); different plans are independent.  Results are deterministic: no floating-point atomics, fixed
  *    accumulation order.
  */
 #ifndef OSSCIR_H
@@ -177,6 +179,20 @@ int osscir_diag_spc_steps(osscir_plan plan, const float *G, double lambda, float
  * no host synchronisation. */
 int osscir_mocca_iterate(osscir_plan plan, const osscir_params *params, osscir_state *state, int32_t n_iter,
                          double *dtpl, osscir_stream stream);
+
+/* One stage of a MOCCA iteration, exactly as osscir_mocca_iterate runs it:
+ *   stage 0  forward projection p = X fbar into the workspace
+ *   stage 1  spectral model, step lengths and dual step (reads p, updates y)
+ *   stage 2  back-projection fused with the primal step (updates f, fbar)
+ * Running stages 0, 1, 2 in order equals one call of osscir_mocca_iterate
+ * with n_iter = 1 and dtpl = NULL.  For callers that time or interleave the
+ * stages. */
+int osscir_mocca_stage(osscir_plan plan, const osscir_params *params, osscir_state *state, int32_t stage,
+                       osscir_stream stream);
+
+/* nnz[l] = number of pixels with X_{l,k} > 0 (the FP32 weights the library
+ * uses), int32 DEVICE array [V][D]. */
+int osscir_ray_nnz(osscir_plan plan, int32_t *nnz, osscir_stream stream);
 
 /* D_TPL(c, chat(f)) of Eq. (DTPL) at maps f [3][n][n], accumulated in FP64
  * in a fixed order, written to the DEVICE double *out.  Needs work. */

@@ -22,7 +22,8 @@ struct osscir_plan_s {
   int device = -1;
   ScanDesc sd{};
   RayLine *d_rays = nullptr;
-  float2 *d_views = nullptr;
+  ViewGeom *d_views = nullptr;
+  void *d_pack = nullptr;  // packed-image scratch of the standalone projector calls
   float *d_rho = nullptr;
   float *d_tab = nullptr;
 };
@@ -53,9 +54,10 @@ int hip_fail(hipError_t e, const char *what) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// workspace regions: p [3][L] f32 | qS [9][L] f32 | partial sums (f64)
+// workspace regions: p [3][L] f32 | qS [9][L] f32 | partial sums (f64) |
+// packed images of the forward projector
 struct WorkLayout {
-  size_t p = 0, qS = 0, partial = 0, total = 0;
+  size_t p = 0, qS = 0, partial = 0, pack = 0, total = 0;
 };
 
 WorkLayout work_layout(const ScanDesc &sd) {
@@ -64,7 +66,8 @@ WorkLayout work_layout(const ScanDesc &sd) {
   w.p = 0;
   w.qS = align256(w.p + 3 * L * sizeof(float));
   w.partial = align256(w.qS + 9 * L * sizeof(float));
-  w.total = align256(w.partial + (size_t)dtpl_partial_count(sd) * sizeof(double));
+  w.pack = align256(w.partial + (size_t)dtpl_partial_count(sd) * sizeof(double));
+  w.total = align256(w.pack + pack_scratch_bytes(sd));
   return w;
 }
 
@@ -82,6 +85,7 @@ void free_plan(osscir_plan p) {
   if (p->d_views) (void)hipFree(p->d_views);
   if (p->d_rho) (void)hipFree(p->d_rho);
   if (p->d_tab) (void)hipFree(p->d_tab);
+  if (p->d_pack) (void)hipFree(p->d_pack);
   delete p;
 }
 
@@ -136,32 +140,32 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   const size_t L = (size_t)V * D;
   const double h = g.pixel_cm;
 
-  // per-ray line parameters (pixel units): normal and offset kept in FP64,
+  // per-view source position and per-ray line parameters, pixel index
+  // coordinates (pixel (ix, iy) centred at (ix, iy)): unit normals in FP64,
   // the trapezoid constants rounded to FP32
+  const double c0 = 0.5 * (N - 1);
   std::vector<RayLine> rays(L);
-  std::vector<float2> views(V);
+  std::vector<ViewGeom> views(V);
   for (int v = 0; v < V; ++v) {
     const double beta = g.view0_rad + g.arc_rad * (double)v / (double)V;
     const double cb = std::cos(beta), sb = std::sin(beta);
-    views[v] = make_float2((float)cb, (float)sb);
-    const double sx = g.sid_cm * cb / h, sy = g.sid_cm * sb / h;
+    const double sx = g.sid_cm * cb / h + c0, sy = g.sid_cm * sb / h + c0;
+    views[v] = ViewGeom{sx, sy, (float)cb, (float)sb, 0.0f, 0.0f};
     for (int d = 0; d < D; ++d) {
       const double u = ((double)d - 0.5 * (D - 1)) * g.bin_cm;
-      const double px = (-(g.sdd_cm - g.sid_cm) * cb - u * sb) / h;
-      const double py = (-(g.sdd_cm - g.sid_cm) * sb + u * cb) / h;
+      const double px = (-(g.sdd_cm - g.sid_cm) * cb - u * sb) / h + c0;
+      const double py = (-(g.sdd_cm - g.sid_cm) * sb + u * cb) / h + c0;
       double tx = px - sx, ty = py - sy;
       const double len = std::sqrt(tx * tx + ty * ty);
       tx /= len;
       ty /= len;
       const double nx = -ty, ny = tx;
-      const double s = nx * sx + ny * sy;
       const double anx = std::fabs(nx), any = std::fabs(ny);
       const double a = 0.5 * (anx + any);
       const double hmax = h / std::max(anx, any);
       const double prod = anx * any;
       const double kappa = (prod * 1e30 > h) ? h / prod : 1e30;
-      const size_t l = (size_t)v * D + d;
-      rays[l] = RayLine{nx, ny, s, (float)a, (float)hmax, (float)kappa, 0.0f};
+      rays[(size_t)v * D + d] = RayLine{nx, ny, (float)a, (float)hmax, (float)kappa, 0.0f};
     }
   }
   // spectral table
@@ -182,14 +186,15 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
 
   hipError_t e;
   if ((e = hipMalloc(&p->d_rays, rays.size() * sizeof(RayLine))) != hipSuccess ||
-      (e = hipMalloc(&p->d_views, views.size() * sizeof(float2))) != hipSuccess ||
+      (e = hipMalloc(&p->d_views, views.size() * sizeof(ViewGeom))) != hipSuccess ||
+      (e = hipMalloc(&p->d_pack, 2 * (size_t)N * N * sizeof(float4))) != hipSuccess ||
       (e = hipMalloc(&p->d_rho, L * sizeof(float))) != hipSuccess ||
       (e = hipMalloc(&p->d_tab, tab.size() * sizeof(float))) != hipSuccess) {
     free_plan(p);
     return fail(OSSCIR_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
   if ((e = hipMemcpy(p->d_rays, rays.data(), rays.size() * sizeof(RayLine), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(p->d_views, views.data(), views.size() * sizeof(float2), hipMemcpyHostToDevice)) !=
+      (e = hipMemcpy(p->d_views, views.data(), views.size() * sizeof(ViewGeom), hipMemcpyHostToDevice)) !=
           hipSuccess ||
       (e = hipMemcpy(p->d_tab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
     free_plan(p);
@@ -202,7 +207,6 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   sd.n_rays = (int)L;
   sd.n_energy = I;
   sd.c0 = 0.5f * (float)(N - 1);
-  sd.c0d = 0.5 * (double)(N - 1);
   sd.sid_px = (float)(g.sid_cm / h);
   sd.bin_scale = (float)(g.sdd_cm / g.bin_cm);
   sd.cbin = 0.5f * (float)(D - 1);
@@ -220,7 +224,7 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   }
   std::vector<float> h_ones((size_t)N * N, 1.0f);
   e = hipMemcpy(ones, h_ones.data(), h_ones.size() * sizeof(float), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_forward(sd, ones, 1, p->d_rho, nullptr);
+  if (e == hipSuccess) e = launch_forward(sd, ones, 1, p->d_rho, p->d_pack, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   (void)hipFree(ones);
   if (e != hipSuccess) {
@@ -258,7 +262,7 @@ int osscir_forward_project(osscir_plan plan, const float *f, int32_t n_ch, float
   int rc = check_plan(plan);
   if (rc) return rc;
   if (!f || !p || n_ch < 1) return fail(OSSCIR_EINVAL, "forward_project: null pointer or n_ch < 1");
-  OSSCIR_HIP(launch_forward(plan->sd, f, n_ch, p, (hipStream_t)stream), "forward_project launch");
+  OSSCIR_HIP(launch_forward(plan->sd, f, n_ch, p, plan->d_pack, (hipStream_t)stream), "forward_project launch");
   return OSSCIR_OK;
 }
 
@@ -304,14 +308,22 @@ int osscir_diag_spc_steps(osscir_plan plan, const float *G, double lambda, float
   return steps_common(plan, G, lambda, sigma, tau, work, work_bytes, false, stream);
 }
 
-int osscir_mocca_iterate(osscir_plan plan, const osscir_params *params, osscir_state *state, int32_t n_iter,
-                         double *dtpl, osscir_stream stream) {
+namespace {
+
+struct IterArgs {
+  float *p, *qS;
+  double *partial;
+  void *pack;
+  bool block, clip, fp64;
+  float lam;
+};
+
+int check_iter(osscir_plan plan, const osscir_params *params, const osscir_state *state, IterArgs *out) {
   int rc = check_plan(plan);
   if (rc) return rc;
-  if (!params || !state) return fail(OSSCIR_EINVAL, "mocca_iterate: null params or state");
-  if (n_iter < 0) return fail(OSSCIR_EINVAL, "n_iter < 0");
+  if (!params || !state) return fail(OSSCIR_EINVAL, "mocca: null params or state");
   if (!state->f || !state->fbar || !state->y || !state->c || !state->work)
-    return fail(OSSCIR_EINVAL, "mocca_iterate: null state buffer");
+    return fail(OSSCIR_EINVAL, "mocca: null state buffer");
   if (!(params->lambda > 0) || !std::isfinite(params->lambda)) return fail(OSSCIR_EINVAL, "lambda must be > 0");
   if (params->precond != OSSCIR_PRECOND_DIAG && params->precond != OSSCIR_PRECOND_BLOCK)
     return fail(OSSCIR_EINVAL, "unknown preconditioner %d", params->precond);
@@ -320,23 +332,68 @@ int osscir_mocca_iterate(osscir_plan plan, const osscir_params *params, osscir_s
   const WorkLayout wl = work_layout(plan->sd);
   if (state->work_bytes < wl.total)
     return fail(OSSCIR_ESTATE, "workspace %zu < %zu bytes", state->work_bytes, wl.total);
+  out->p = (float *)((char *)state->work + wl.p);
+  out->qS = (float *)((char *)state->work + wl.qS);
+  out->partial = (double *)((char *)state->work + wl.partial);
+  out->pack = (char *)state->work + wl.pack;
+  out->block = params->precond == OSSCIR_PRECOND_BLOCK;
+  out->clip = params->curvature == OSSCIR_CURV_CLIP;
+  out->fp64 = params->fp64_small != 0;
+  out->lam = (float)params->lambda;
+  return OSSCIR_OK;
+}
+
+int run_stage(const ScanDesc &sd, const IterArgs &a, osscir_state *state, int stage, hipStream_t st) {
+  switch (stage) {
+    case 0:
+      OSSCIR_HIP(launch_forward(sd, state->fbar, 3, a.p, a.pack, st), "mocca: forward projection");
+      break;
+    case 1:
+      OSSCIR_HIP(launch_spectral_dual(sd, a.p, state->c, state->y, a.qS, a.lam, a.clip, a.block, a.fp64, st),
+                 "mocca: spectral model and dual step");
+      break;
+    case 2:
+      OSSCIR_HIP(launch_back_primal(sd, a.qS, state->f, state->fbar, a.lam, a.block, a.fp64, st),
+                 "mocca: back-projection and primal step");
+      break;
+    default:
+      return fail(OSSCIR_EINVAL, "unknown stage %d", stage);
+  }
+  return OSSCIR_OK;
+}
+
+}  // namespace
+
+int osscir_mocca_iterate(osscir_plan plan, const osscir_params *params, osscir_state *state, int32_t n_iter,
+                         double *dtpl, osscir_stream stream) {
+  IterArgs a;
+  int rc = check_iter(plan, params, state, &a);
+  if (rc) return rc;
+  if (n_iter < 0) return fail(OSSCIR_EINVAL, "n_iter < 0");
   const ScanDesc &sd = plan->sd;
   hipStream_t st = (hipStream_t)stream;
-  float *p = (float *)((char *)state->work + wl.p);
-  float *qS = (float *)((char *)state->work + wl.qS);
-  double *partial = (double *)((char *)state->work + wl.partial);
-  const bool block = params->precond == OSSCIR_PRECOND_BLOCK;
-  const bool clip = params->curvature == OSSCIR_CURV_CLIP;
-  const bool fp64 = params->fp64_small != 0;
-  const float lam = (float)params->lambda;
   for (int it = 0; it < n_iter; ++it) {
-    OSSCIR_HIP(launch_forward(sd, state->fbar, 3, p, st), "mocca: forward projection");
-    OSSCIR_HIP(launch_spectral_dual(sd, p, state->c, state->y, qS, lam, clip, block, fp64, st),
-               "mocca: spectral model and dual step");
-    OSSCIR_HIP(launch_back_primal(sd, qS, state->f, state->fbar, lam, block, fp64, st),
-               "mocca: back-projection and primal step");
-    if (dtpl) OSSCIR_HIP(launch_dtpl(sd, state->f, state->c, p, partial, dtpl + it, st), "mocca: D_TPL");
+    for (int stage = 0; stage < 3; ++stage)
+      if ((rc = run_stage(sd, a, state, stage, st))) return rc;
+    if (dtpl)
+      OSSCIR_HIP(launch_dtpl(sd, state->f, state->c, a.p, a.pack, a.partial, dtpl + it, st), "mocca: D_TPL");
   }
+  return OSSCIR_OK;
+}
+
+int osscir_mocca_stage(osscir_plan plan, const osscir_params *params, osscir_state *state, int32_t stage,
+                       osscir_stream stream) {
+  IterArgs a;
+  int rc = check_iter(plan, params, state, &a);
+  if (rc) return rc;
+  return run_stage(plan->sd, a, state, stage, (hipStream_t)stream);
+}
+
+int osscir_ray_nnz(osscir_plan plan, int32_t *nnz, osscir_stream stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!nnz) return fail(OSSCIR_EINVAL, "null nnz");
+  OSSCIR_HIP(launch_count(plan->sd, nnz, (hipStream_t)stream), "ray_nnz launch");
   return OSSCIR_OK;
 }
 
@@ -349,7 +406,8 @@ int osscir_dtpl(osscir_plan plan, const float *f, const float *c, double *out, v
   if (work_bytes < wl.total) return fail(OSSCIR_ESTATE, "workspace %zu < %zu bytes", work_bytes, wl.total);
   float *p = (float *)((char *)work + wl.p);
   double *partial = (double *)((char *)work + wl.partial);
-  OSSCIR_HIP(launch_dtpl(plan->sd, f, c, p, partial, out, (hipStream_t)stream), "dtpl launch");
+  OSSCIR_HIP(launch_dtpl(plan->sd, f, c, p, (char *)work + wl.pack, partial, out, (hipStream_t)stream),
+             "dtpl launch");
   return OSSCIR_OK;
 }
 

@@ -14,11 +14,11 @@ namespace osscir {
 
 // ---------------------------------------------------------------- projector
 //
-// A ray is the line {(X, Y) : nx X + ny Y = s} in pixel units relative to the
-// image centre ((nx, ny) a unit normal).  The chord of that line through the
-// unit square centred at (X, Y) depends only on the signed distance
-// sig = s - nx X - ny Y of the square's centre from the line: it is the
-// trapezoid  min(hmax, max(0, (a - |sig|) kappa))  with
+// A ray is a line through the source S of its view with unit normal
+// (nx, ny).  The chord of that line through the unit square centred at P
+// depends only on the signed distance sig = n . (S - P) of the square's
+// centre from the line: it is the trapezoid
+//   min(hmax, max(0, (a - |sig|) kappa))  with
 //   a     = (|nx| + |ny|) / 2           (half-width of the square's shadow)
 //   kappa = 1 / (|nx| |ny|)             (slope of the corner-cutting part)
 //   hmax  = 1 / max(|nx|, |ny|)         (chord through a full column/row)
@@ -26,17 +26,20 @@ namespace osscir {
 // line-intersection length X_{l,k} (the chord of the square, Sec. II's
 // "projection along ray l"), evaluated branch-free.
 //
-// sig is the difference of numbers as large as the image half-diagonal, so
-// it is formed in FP64 (two FMAs) and rounded once; the trapezoid is FP32.
+// Coordinates are pixel units with pixel (ix, iy) centred at (ix, iy); the
+// caller passes dx = Sx - ix, dy = Sy - iy in FP64 (sig is a difference of
+// numbers as large as the source distance), sig is rounded once to FP32 and
+// the trapezoid is FP32.
 struct RayLine {
-  double nx, ny, s;
+  double nx, ny;
   float a, hmax, kappa, pad;
 };
 
-__device__ __forceinline__ float chord_weight(const RayLine &r, double X, double Y) {
-  const double sig = fma(-r.ny, Y, fma(-r.nx, X, r.s));
-  const float t = (r.a - fabsf((float)sig)) * r.kappa;
-  return fminf(r.hmax, fmaxf(0.0f, t));
+__device__ __forceinline__ float chord_weight(double nx, double ny, float a, float hmax, float kappa, double dx,
+                                              double dy) {
+  const double sig = fma(nx, dx, ny * dy);
+  const float t = (a - fabsf((float)sig)) * kappa;
+  return fminf(hmax, fmaxf(0.0f, t));
 }
 
 // ---------------------------------------------------------------- softexp

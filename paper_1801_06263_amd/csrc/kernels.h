@@ -11,6 +11,14 @@ namespace osscir {
 
 struct RayLine;
 
+// Per-view geometry: source position in pixel index coordinates (pixel
+// (ix, iy) centred at (ix, iy)), and the view direction for the detector
+// projection of pixel corners.
+struct ViewGeom {
+  double sx, sy;
+  float cb, sb, pad0, pad1;
+};
+
 constexpr int kMat = 3;   // materials (block SPC works on 3x3 blocks)
 constexpr int kWin = 4;   // energy windows
 constexpr int kTab = 48;  // floats per energy in the spectral table
@@ -31,13 +39,12 @@ struct ScanDesc {
   int n_rays;        // n_views * n_bins
   int n_energy;
   float c0;          // (n - 1) / 2
-  double c0d;        // (n - 1) / 2
   float sid_px;      // source-isocentre distance, pixel units
   float bin_scale;   // sdd / bin pitch (bins per unit tan)
   float cbin;        // (n_bins - 1) / 2
   float n0[kWin];    // incident counts per window
   const struct RayLine *rays;  // [L]
-  const float2 *views;  // [V] (cos beta, sin beta)
+  const ViewGeom *views;        // [V]
   const float *rho;     // [L]
   const float *tab;     // [I][kTab]
 };

@@ -6,10 +6,17 @@
 
 namespace osscir {
 
-// p[c][l] = sum_k X_{l,k} f[c][k], c < nch (chunks of up to 3 channels).
-hipError_t launch_forward(const ScanDesc &sd, const float *f, int nch, float *p, hipStream_t st);
+// Bytes of the packed-image scratch the forward projector needs.
+size_t pack_scratch_bytes(const ScanDesc &sd);
+
+// p[c][l] = sum_k X_{l,k} f[c][k], c < nch (chunks of up to 3 channels);
+// pack: device scratch of pack_scratch_bytes().
+hipError_t launch_forward(const ScanDesc &sd, const float *f, int nch, float *p, void *pack, hipStream_t st);
 
 // b[c][k] = sum_l X_{l,k} q[c][l] (chunks of 9, 6, 3, 2 or 1 channels).
 hipError_t launch_back(const ScanDesc &sd, const float *q, int nch, float *b, hipStream_t st);
+
+// nnz[l] = number of pixels with a non-zero weight on ray l.
+hipError_t launch_count(const ScanDesc &sd, int *nnz, hipStream_t st);
 
 }  // namespace osscir

@@ -23,7 +23,7 @@ hipError_t launch_steps(const ScanDesc &sd, const float *G, float lambda, bool b
                         float *out_img, hipStream_t st);
 
 int dtpl_partial_count(const ScanDesc &sd);
-hipError_t launch_dtpl(const ScanDesc &sd, const float *f, const float *c, float *p_scratch, double *partial,
-                       double *out, hipStream_t st);
+hipError_t launch_dtpl(const ScanDesc &sd, const float *f, const float *c, float *p_scratch, void *pack,
+                       double *partial, double *out, hipStream_t st);
 
 }  // namespace osscir

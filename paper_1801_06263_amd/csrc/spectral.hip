@@ -17,9 +17,13 @@ namespace osscir {
 // upper-triangle index of (m, n), m <= n, in a symmetric 3x3
 __device__ __forceinline__ constexpr int ut(int m, int n) { return m == 0 ? n : (m == 1 ? 2 + n : 5); }
 
-template <bool NEED_A, bool NEED_HB>
+// SHIFT: the sums are taken with exp(-(z - zshift)) in place of exp(-z), for
+// a ray whose every z_i >= zshift > 0 (all energies on the exponential
+// branch).  The ratios a_w / g_w and Hb_w / g_w are unchanged; g_w carries
+// the factor exp(zshift).
+template <bool NEED_A, bool NEED_HB, bool SHIFT = false>
 __device__ __forceinline__ void energy_sums(const ScanDesc &sd, float p0, float p1, float p2, float g[kWin],
-                                            float a[kWin * kMat], float hb[kWin * 6]) {
+                                            float a[kWin * kMat], float hb[kWin * 6], float zshift = 0.0f) {
 #pragma unroll
   for (int w = 0; w < kWin; ++w) g[w] = 0.0f;
   if (NEED_A) {
@@ -33,9 +37,14 @@ __device__ __forceinline__ void energy_sums(const ScanDesc &sd, float p0, float 
   const float *__restrict__ tab = sd.tab;
   for (int i = 0; i < sd.n_energy; ++i) {
     const float *t = tab + i * kTab;
-    const float z = __fmaf_rn(t[kTabMu + 2], p2, __fmaf_rn(t[kTabMu + 1], p1, t[kTabMu] * p0));
     float E, E1, E2;
-    softexp3(z, E, E1, E2);
+    if (SHIFT) {
+      const float zs = __fmaf_rn(t[kTabMu + 2], p2, __fmaf_rn(t[kTabMu + 1], p1, __fmaf_rn(t[kTabMu], p0, -zshift)));
+      E = E1 = E2 = __expf(-zs);
+    } else {
+      const float z = __fmaf_rn(t[kTabMu + 2], p2, __fmaf_rn(t[kTabMu + 1], p1, t[kTabMu] * p0));
+      softexp3(z, E, E1, E2);
+    }
 #pragma unroll
     for (int w = 0; w < kWin; ++w) g[w] = __fmaf_rn(t[kTabS + w], E, g[w]);
     if (NEED_A) {
@@ -47,6 +56,26 @@ __device__ __forceinline__ void energy_sums(const ScanDesc &sd, float p0, float 
       for (int j = 0; j < kWin * 6; ++j) hb[j] = __fmaf_rn(t[kTabSMuMu + j], E2, hb[j]);
     }
   }
+}
+
+// Model sums of one ray with a rescue for transmissions below FP32 range:
+// if a window sum underflows (an iterate far outside the physical range),
+// the sums are recomputed with the exponent shifted by min_i z_i.  Returns
+// the factor (<= 1) that turns the returned g_w into the true sums.
+template <bool NEED_A, bool NEED_HB>
+__device__ __forceinline__ float energy_sums_safe(const ScanDesc &sd, float p0, float p1, float p2, float g[kWin],
+                                                  float a[kWin * kMat], float hb[kWin * 6]) {
+  energy_sums<NEED_A, NEED_HB>(sd, p0, p1, p2, g, a, hb);
+  const float gmin = fminf(fminf(g[0], g[1]), fminf(g[2], g[3]));
+  if (gmin >= 1e-30f) return 1.0f;
+  float zmin = 3.0e38f;
+  for (int i = 0; i < sd.n_energy; ++i) {
+    const float *t = sd.tab + i * kTab;
+    zmin = fminf(zmin, __fmaf_rn(t[kTabMu + 2], p2, __fmaf_rn(t[kTabMu + 1], p1, t[kTabMu] * p0)));
+  }
+  if (!(zmin > 0.0f)) return 1.0f;  // some energy on the linear branch: no underflow possible
+  energy_sums<NEED_A, NEED_HB, true>(sd, p0, p1, p2, g, a, hb, zmin);
+  return __expf(-zmin);
 }
 
 // Per-ray p-space Hessian  H = sum_w c_w a_w a_w^T - sum_w (r_w / g_w) Hb_w
@@ -77,11 +106,11 @@ __global__ void __launch_bounds__(256) k_spectral_model(ScanDesc sd, const float
   const int L = sd.n_rays;
   if (l >= L) return;
   float g[kWin], af[kWin * kMat], hb[kWin * 6];
-  energy_sums<true, true>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb);
+  const float scale = energy_sums_safe<true, true>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb);
   T a[kWin][kMat], cw[kWin], rg[kWin];
 #pragma unroll
   for (int w = 0; w < kWin; ++w) {
-    const float ch = sd.n0[w] * g[w];
+    const float ch = sd.n0[w] * g[w] * scale;
     const float rw = c[w * L + l] - ch;
     if (chat) chat[w * L + l] = ch;
     if (r) r[w * L + l] = rw;
@@ -130,14 +159,14 @@ __global__ void __launch_bounds__(256) k_spectral_dual(ScanDesc sd, const float 
     return;
   }
   float g[kWin], af[kWin * kMat], hb[kWin * 6];
-  energy_sums<true, CLIP>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb);
+  const float scale = energy_sums_safe<true, CLIP>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb);
 
   T a[kWin][kMat], cw[kWin], rw[kWin], yw[kWin], sig[kWin];
 #pragma unroll
   for (int w = 0; w < kWin; ++w) {
     const float cf = c[w * L + l];
     cw[w] = (T)cf;
-    rw[w] = (T)(cf - sd.n0[w] * g[w]);
+    rw[w] = (T)(cf - sd.n0[w] * g[w] * scale);
     yw[w] = (T)y[w * L + l];
     const T ig = T(1) / (T)g[w];
 #pragma unroll
@@ -313,12 +342,13 @@ __global__ void k_scale_steps(int count, float lambda, float *__restrict__ v) {
 template <bool BLOCK>
 __global__ void __launch_bounds__(256) k_back_primal(ScanDesc sd, const float *__restrict__ qS,
                                                       float *__restrict__ f, float *__restrict__ fbar, float lambda) {
-  const int ix = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int iy = blockIdx.y * 16 + (threadIdx.x >> 4);
-  if (ix >= sd.n || iy >= sd.n) return;
+  __shared__ BpShared sh;
   constexpr int NCH = BLOCK ? 9 : 6;
   double acc[NCH];
-  back_accumulate<NCH>(sd, ix, iy, qS, sd.n_rays, acc);
+  back_accumulate<NCH>(sd, blockIdx.x, blockIdx.y, qS, sd.n_rays, acc, sh);
+  const int ix = blockIdx.x * kBpTile + (threadIdx.x & (kBpTile - 1));
+  const int iy = blockIdx.y * kBpTile + (threadIdx.x / kBpTile);
+  if (ix >= sd.n || iy >= sd.n) return;
   const int nn = sd.n * sd.n;
   const int k = iy * sd.n + ix;
   float fo[3], fn[3];
@@ -385,7 +415,9 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double *__restrict__
 // ---------------------------------------------------------------- launchers
 
 static inline dim3 ray_grid(const ScanDesc &sd) { return dim3((sd.n_rays + 255) / 256); }
-static inline dim3 pix_grid(const ScanDesc &sd) { return dim3((sd.n + 15) / 16, (sd.n + 15) / 16); }
+static inline dim3 pix_grid(const ScanDesc &sd) {
+  return dim3((sd.n + kBpTile - 1) / kBpTile, (sd.n + kBpTile - 1) / kBpTile);
+}
 
 hipError_t launch_spectral_model(const ScanDesc &sd, const float *p, const float *c, float *chat, float *r,
                                  float *G, float *H, float *Hp, bool fp64, hipStream_t st) {
@@ -448,9 +480,9 @@ hipError_t launch_steps(const ScanDesc &sd, const float *G, float lambda, bool b
 
 int dtpl_partial_count(const ScanDesc &sd) { return (sd.n_rays + 255) / 256; }
 
-hipError_t launch_dtpl(const ScanDesc &sd, const float *f, const float *c, float *p_scratch, double *partial,
-                       double *out, hipStream_t st) {
-  hipError_t e = launch_forward(sd, f, 3, p_scratch, st);
+hipError_t launch_dtpl(const ScanDesc &sd, const float *f, const float *c, float *p_scratch, void *pack,
+                       double *partial, double *out, hipStream_t st) {
+  hipError_t e = launch_forward(sd, f, 3, p_scratch, pack, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dtpl_partial, ray_grid(sd), dim3(256), 0, st, sd, p_scratch, c, partial);
   e = hipGetLastError();

@@ -60,6 +60,8 @@ SIGNATURES = {
                                         c_void_p]),
     "osscir_mocca_iterate": (c_int32, [c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_State), c_int32, c_void_p,
                                        c_void_p]),
+    "osscir_mocca_stage": (c_int32, [c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_State), c_int32, c_void_p]),
+    "osscir_ray_nnz": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "osscir_dtpl": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "osscir_last_error": (ctypes.c_char_p, []),
     "osscir_version": (ctypes.c_char_p, []),
@@ -239,19 +241,37 @@ class Plan:
         return State(f=f, fbar=f.clone(), y=torch.zeros(4, *self.sino_shape, dtype=torch.float32, device="cuda"),
                      c=c.to(device="cuda", dtype=torch.float32).contiguous(), work=self.workspace())
 
+    def _c_state(self, state: State) -> _State:
+        import torch
+        V, D = self.sino_shape
+        return _State(_dev(state.f, (3, self.n, self.n), torch.float32, "f").value,
+                      _dev(state.fbar, (3, self.n, self.n), torch.float32, "fbar").value,
+                      _dev(state.y, (4, V, D), torch.float32, "y").value,
+                      _dev(state.c, (4, V, D), torch.float32, "c").value,
+                      _dev(state.work, None, torch.uint8, "work").value, state.work.numel())
+
     def mocca_iterate(self, state: State, params: Params, n_iter: int, dtpl: bool = False, stream=None):
         """Run n_iter iterations in place; returns a [n_iter] float64 device tensor of D_TPL if asked."""
         import torch
-        V, D = self.sino_shape
-        st = _State(_dev(state.f, (3, self.n, self.n), torch.float32, "f").value,
-                    _dev(state.fbar, (3, self.n, self.n), torch.float32, "fbar").value,
-                    _dev(state.y, (4, V, D), torch.float32, "y").value,
-                    _dev(state.c, (4, V, D), torch.float32, "c").value,
-                    _dev(state.work, None, torch.uint8, "work").value, state.work.numel())
+        st = self._c_state(state)
         out = torch.empty(max(n_iter, 1), dtype=torch.float64, device="cuda") if dtpl else None
         prm = params.to_c()
         _check(_lib.osscir_mocca_iterate(self._h, ctypes.byref(prm), ctypes.byref(st), int(n_iter),
                                          _dev(out) if dtpl else None, _stream_handle(stream)))
+        return out
+
+    def mocca_stage(self, state: State, params: Params, stage: int, stream=None):
+        """One stage (0 forward projection, 1 spectral + dual, 2 back-projection + primal)."""
+        st = self._c_state(state)
+        prm = params.to_c()
+        _check(_lib.osscir_mocca_stage(self._h, ctypes.byref(prm), ctypes.byref(st), int(stage),
+                                       _stream_handle(stream)))
+
+    def ray_nnz(self, stream=None):
+        """Number of pixels each ray crosses (int32 [V, D] device tensor)."""
+        import torch
+        out = torch.empty(*self.sino_shape, dtype=torch.int32, device="cuda")
+        _check(_lib.osscir_ray_nnz(self._h, _dev(out), _stream_handle(stream)))
         return out
 
     def dtpl(self, f, c, work=None, stream=None):
