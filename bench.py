@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--fp64-small", type=int, default=0)
     ap.add_argument("--lam", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", default="12,36", help="view-subset sizes of the oracle sample")
+    ap.add_argument("--cpu-views", default="24,72", help="view-subset sizes of the oracle sample")
     ap.add_argument("--json-out", default=None)
     return ap.parse_args()
 

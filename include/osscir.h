@@ -17,7 +17,7 @@
  *  - Every data pointer argument is a DEVICE pointer owned by the caller
  *    (allocated on the device the plan was created on), unless documented
  *    "host".  The library allocates device memory only inside
- *    osscir_plan_create (its constant tables, ray geometry and a 32 n^2-byte
+ *    osscir_plan_create (its constant tables, ray geometry and a 32 (n+8)^2-byte
  *    image scratch used by osscir_forward_project) and frees it in
  *    osscir_plan_destroy; it keeps no pointer to caller memory after a call
  *    returns.

@@ -187,7 +187,7 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   hipError_t e;
   if ((e = hipMalloc(&p->d_rays, rays.size() * sizeof(RayLine))) != hipSuccess ||
       (e = hipMalloc(&p->d_views, views.size() * sizeof(ViewGeom))) != hipSuccess ||
-      (e = hipMalloc(&p->d_pack, 2 * (size_t)N * N * sizeof(float4))) != hipSuccess ||
+      (e = hipMalloc(&p->d_pack, 2 * (size_t)(N + 2 * kPad) * (N + 2 * kPad) * sizeof(float4))) != hipSuccess ||
       (e = hipMalloc(&p->d_rho, L * sizeof(float))) != hipSuccess ||
       (e = hipMalloc(&p->d_tab, tab.size() * sizeof(float))) != hipSuccess) {
     free_plan(p);

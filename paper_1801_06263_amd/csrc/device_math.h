@@ -39,7 +39,7 @@ __device__ __forceinline__ float chord_weight(double nx, double ny, float a, flo
                                               double dy) {
   const double sig = fma(nx, dx, ny * dy);
   const float t = (a - fabsf((float)sig)) * kappa;
-  return fminf(hmax, fmaxf(0.0f, t));
+  return __builtin_amdgcn_fmed3f(t, 0.0f, hmax);  // clamp to [0, hmax]
 }
 
 // ---------------------------------------------------------------- softexp

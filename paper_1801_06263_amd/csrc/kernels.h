@@ -22,6 +22,7 @@ struct ViewGeom {
 constexpr int kMat = 3;   // materials (block SPC works on 3x3 blocks)
 constexpr int kWin = 4;   // energy windows
 constexpr int kTab = 48;  // floats per energy in the spectral table
+constexpr int kPad = 4;   // zero border of the packed images of the forward projector
 
 // Spectral table, one row of kTab floats per energy i:
 //   [0..2]   mu_{m,i}

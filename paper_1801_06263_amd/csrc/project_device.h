@@ -2,21 +2,23 @@
 // back-projection kernel and the kernels that fuse an epilogue (primal step,
 // step lengths) into it.
 //
-// A workgroup owns a 16 x 16 pixel tile, one thread per pixel.  For each view
-// (in order):
-//   1. one thread projects the tile's four corners onto the detector: every
-//      ray that meets the tile has its bin inside that shadow (+0.05 bin);
-//   2. the workgroup stages those bins' line parameters and the NCH input
-//      values into LDS (coalesced reads of consecutive bins);
-//   3. each thread bounds its own pixel's shadow (the linearised projection
-//      of the pixel centre, widened to cover the exact corner projections,
-//      +0.02 bin) and accumulates w * q over the staged bins in that range.
-// The weights are chord_weight() of the same FP32/FP64 inputs as the forward
-// projector, so the result is X^T q with X's exact weights.  The few products
-// of one view are summed in FP32; the running sum over views is FP64, so the
-// result carries the rounding of the FP32 weights and inputs only (the
-// per-pixel 3x3 step blocks built from it are ill-conditioned, and FP32
-// accumulation over thousands of rays would shift the MOCCA trajectory).
+// A workgroup owns a 16 x 16 pixel tile, one thread per pixel, and walks the
+// views in order.  For a chunk of views at a time, one thread per view
+// projects the tile's four corners onto the detector: every ray that meets
+// the tile has its bin inside that shadow (+0.05 bin), and the same corners
+// bound the half-width of every pixel's own shadow in that view.  The bins of
+// a view (line parameters and the NCH input values) are staged in LDS; the
+// loads of view v+1 are issued before view v is processed and stored after,
+// so each view costs one barrier.  Each thread then projects its pixel centre
+// (one reciprocal), takes the bins within the bounded half-width (+0.02 bin)
+// and accumulates w * q.
+//
+// The weights are chord_weight() of the same inputs as the forward
+// projector, so the result is X^T q with X's exact weights.  Products are
+// summed in FP32 over 8 views at a time and the running sum over views is
+// FP64, so the result carries the rounding of the FP32 weights and inputs
+// only (the per-pixel 3x3 step blocks built from it are ill-conditioned, and
+// FP32 accumulation over thousands of rays would shift the MOCCA trajectory).
 #pragma once
 
 #include "device_math.h"
@@ -25,7 +27,10 @@
 namespace osscir {
 
 constexpr int kBpTile = 16;
-constexpr int kBpMaxBins = 128;  // bins staged at once; wider shadows are processed in chunks
+constexpr int kBpThreads = kBpTile * kBpTile;
+constexpr int kBpMaxBins = 128;   // bins staged per view; wider shadows take a chunked path
+constexpr int kBpViewChunk = kBpThreads;
+constexpr int kBpFlush = 8;       // views summed in FP32 before the FP64 running sum
 
 struct BinLDS {
   double2 n;   // nx, ny
@@ -34,15 +39,97 @@ struct BinLDS {
   float4 w2;   // q5..q8
 };
 
-struct BpShared {
-  BinLDS bins[kBpMaxBins];
-  int range[2][2];  // by view parity: written by thread 0, read by all after a barrier
+struct ViewTile {
+  int d0, d1;    // bins whose rays can meet the tile
+  float hw;      // bound on a pixel's shadow half-width (bins), incl. margin; < 0: use [d0, d1]
+  float pad;
 };
 
-__device__ __forceinline__ float bin_coord(const ScanDesc &sd, const ViewGeom &vg, float X, float Y) {
-  const float num = -vg.sb * X + vg.cb * Y;
-  const float den = sd.sid_px - vg.cb * X - vg.sb * Y;
-  return num / den * sd.bin_scale + sd.cbin;
+struct BpShared {
+  BinLDS bins[2][kBpMaxBins];
+  ViewTile vt[kBpViewChunk];
+};
+
+__device__ __forceinline__ void tile_view_bounds(const ScanDesc &sd, const ViewGeom &vg, int tile_x, int tile_y,
+                                                 ViewTile &out) {
+  const int nb = sd.n_bins;
+  const float x0 = (float)(tile_x * kBpTile) - sd.c0 - 0.5f, x1 = x0 + (float)kBpTile;
+  const float y0 = (float)(tile_y * kBpTile) - sd.c0 - 0.5f, y1 = y0 + (float)kBpTile;
+  float tmin = 3.0e38f, tmax = -3.0e38f, dmin = 3.0e38f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float X = (k & 1) ? x1 : x0;
+    const float Y = (k & 2) ? y1 : y0;
+    const float num = -vg.sb * X + vg.cb * Y;
+    const float den = sd.sid_px - vg.cb * X - vg.sb * Y;
+    const float t = num / den;
+    tmin = fminf(tmin, t);
+    tmax = fmaxf(tmax, t);
+    dmin = fminf(dmin, den);
+  }
+  float lo = fminf(fmaxf(tmin * sd.bin_scale + sd.cbin, -2.0f), (float)nb + 1.0f);
+  float hi = fminf(fmaxf(tmax * sd.bin_scale + sd.cbin, -2.0f), (float)nb + 1.0f);
+  out.d0 = max(0, (int)ceilf(lo - 0.05f));
+  out.d1 = min(nb - 1, (int)floorf(hi + 0.05f));
+  // d t / d X = (-sb + cb t) / den, d t / d Y = (cb + sb t) / den; linear in t,
+  // so bounded by the tile's extreme t; den >= dmin at every pixel centre; the
+  // exact corner offsets exceed the linearised ones by at most a factor
+  // 1 + 1.5 / den (a corner moves den by <= 0.71).
+  if (dmin > 4.0f) {
+    const float A = fmaxf(fabsf(-vg.sb + vg.cb * tmin), fabsf(-vg.sb + vg.cb * tmax));
+    const float B = fmaxf(fabsf(vg.cb + vg.sb * tmin), fabsf(vg.cb + vg.sb * tmax));
+    out.hw = 0.5f * (A + B) / dmin * (1.0f + 1.5f / dmin) * sd.bin_scale + 0.02f;
+  } else {
+    out.hw = -1.0f;
+  }
+}
+
+template <int NCH>
+struct BinRegs {
+  RayLine r;
+  float q[NCH];
+};
+
+template <int NCH>
+__device__ __forceinline__ void bin_load(const ScanDesc &sd, const float *__restrict__ q, int q_stride, int l,
+                                         BinRegs<NCH> &b) {
+  b.r = sd.rays[l];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) b.q[c] = q[c * q_stride + l];
+}
+
+template <int NCH>
+__device__ __forceinline__ void bin_store(const BinRegs<NCH> &b, BinLDS &e) {
+  float qq[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) qq[c] = c < NCH ? b.q[c] : 0.0f;
+  e.n = make_double2(b.r.nx, b.r.ny);
+  e.w0 = make_float4(b.r.a, b.r.hmax, b.r.kappa, qq[0]);
+  e.w1 = make_float4(qq[1], qq[2], qq[3], qq[4]);
+  e.w2 = make_float4(qq[5], qq[6], qq[7], qq[8]);
+}
+
+template <int NCH>
+__device__ __forceinline__ void accumulate_bins(const BinLDS *__restrict__ bins, int b0, int b1, double dx, double dy,
+                                                float part[NCH]) {
+  for (int b = b0; b <= b1; ++b) {
+    const BinLDS &e = bins[b];
+    const double2 nn = e.n;
+    const float4 w0 = e.w0;
+    const float w = chord_weight(nn.x, nn.y, w0.x, w0.y, w0.z, dx, dy);
+    float qv[9];
+    qv[0] = w0.w;
+    if (NCH > 1) {
+      const float4 w1 = e.w1;
+      qv[1] = w1.x; qv[2] = w1.y; qv[3] = w1.z; qv[4] = w1.w;
+    }
+    if (NCH > 5) {
+      const float4 w2 = e.w2;
+      qv[5] = w2.x; qv[6] = w2.y; qv[7] = w2.z; qv[8] = w2.w;
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) part[c] = __fmaf_rn(w, qv[c], part[c]);
+  }
 }
 
 template <int NCH>
@@ -52,94 +139,91 @@ __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, 
   const int tid = threadIdx.x;
   const int ix = tile_x * kBpTile + (tid & (kBpTile - 1));
   const int iy = tile_y * kBpTile + (tid / kBpTile);
-  const int n = sd.n, nb = sd.n_bins;
+  const int n = sd.n, nb = sd.n_bins, V = sd.n_views;
   const bool inside = ix < n && iy < n;
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
   const float X = (float)ix - sd.c0;  // centred, for the detector projection
   const float Y = (float)iy - sd.c0;
-  for (int v = 0; v < sd.n_views; ++v) {
-    const ViewGeom vg = sd.views[v];
-    if (tid == 0) {
-      const float x0 = (float)(tile_x * kBpTile) - sd.c0 - 0.5f, x1 = x0 + (float)kBpTile;
-      const float y0 = (float)(tile_y * kBpTile) - sd.c0 - 0.5f, y1 = y0 + (float)kBpTile;
-      const float b00 = bin_coord(sd, vg, x0, y0), b01 = bin_coord(sd, vg, x0, y1);
-      const float b10 = bin_coord(sd, vg, x1, y0), b11 = bin_coord(sd, vg, x1, y1);
-      float lo = fminf(fminf(b00, b01), fminf(b10, b11));
-      float hi = fmaxf(fmaxf(b00, b01), fmaxf(b10, b11));
-      lo = fminf(fmaxf(lo, -2.0f), (float)nb + 1.0f);
-      hi = fminf(fmaxf(hi, -2.0f), (float)nb + 1.0f);
-      sh.range[v & 1][0] = max(0, (int)ceilf(lo - 0.05f));
-      sh.range[v & 1][1] = min(nb - 1, (int)floorf(hi + 0.05f));
+  float part[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    acc[c] = 0.0;
+    part[c] = 0.0f;
+  }
+  int since_flush = 0;
+  for (int vc = 0; vc < V; vc += kBpViewChunk) {
+    const int cnt = min(kBpViewChunk, V - vc);
+    __syncthreads();  // the previous chunk's last view is done with sh
+    if (tid < cnt) tile_view_bounds(sd, sd.views[vc + tid], tile_x, tile_y, sh.vt[tid]);
+    __syncthreads();
+    // stage the chunk's first view
+    {
+      const ViewTile vt = sh.vt[0];
+      const int nbv = vt.d1 - vt.d0 + 1;
+      if (nbv <= kBpMaxBins && tid < nbv) {
+        BinRegs<NCH> b;
+        bin_load<NCH>(sd, q, q_stride, vc * nb + vt.d0 + tid, b);
+        bin_store<NCH>(b, sh.bins[0][tid]);
+      }
     }
     __syncthreads();
-    const int D0 = sh.range[v & 1][0], D1 = sh.range[v & 1][1];
-    // this pixel's candidate bins
-    int dlo = D0, dhi = D1;
-    {
-      const float num = -vg.sb * X + vg.cb * Y;
-      const float den = sd.sid_px - vg.cb * X - vg.sb * Y;
-      if (den > 4.0f) {
-        const float rden = 1.0f / den;
-        const float t = num * rden;
-        const float dtx = (-vg.sb + vg.cb * t) * rden;
-        const float dty = (vg.cb + vg.sb * t) * rden;
-        const float hw = 0.5f * (fabsf(dtx) + fabsf(dty)) * (1.0f + 1.5f * rden) * sd.bin_scale;
-        const float bc = t * sd.bin_scale + sd.cbin;
-        const float lo = fminf(fmaxf(bc - hw, -2.0f), (float)nb + 1.0f);
-        const float hi = fminf(fmaxf(bc + hw, -2.0f), (float)nb + 1.0f);
-        dlo = max(dlo, (int)ceilf(lo - 0.02f));
-        dhi = min(dhi, (int)floorf(hi + 0.02f));
+    for (int j = 0; j < cnt; ++j) {
+      const int v = vc + j;
+      const int cur = j & 1;
+      const ViewTile vt = sh.vt[j];
+      const int nbv = vt.d1 - vt.d0 + 1;
+      // issue the next view's loads
+      BinRegs<NCH> nxt;
+      bool have_next = false;
+      if (j + 1 < cnt) {
+        const ViewTile vn = sh.vt[j + 1];
+        const int nbn = vn.d1 - vn.d0 + 1;
+        have_next = nbn <= kBpMaxBins && tid < nbn;
+        if (have_next) bin_load<NCH>(sd, q, q_stride, (v + 1) * nb + vn.d0 + tid, nxt);
       }
-    }
-    const double dx = vg.sx - (double)ix;
-    const double dy = vg.sy - (double)iy;
-    for (int c0 = D0; c0 <= D1; c0 += kBpMaxBins) {
-      const int c1 = min(D1, c0 + kBpMaxBins - 1);
-      // stage bins c0..c1
-      for (int b = tid; b <= c1 - c0; b += blockDim.x) {
-        const int l = v * nb + c0 + b;
-        const RayLine r = sd.rays[l];
-        float qq[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) qq[c] = c < NCH ? q[c * q_stride + l] : 0.0f;
-        BinLDS e;
-        e.n = make_double2(r.nx, r.ny);
-        e.w0 = make_float4(r.a, r.hmax, r.kappa, qq[0]);
-        e.w1 = make_float4(qq[1], qq[2], qq[3], qq[4]);
-        e.w2 = make_float4(qq[5], qq[6], qq[7], qq[8]);
-        sh.bins[b] = e;
-      }
-      __syncthreads();
-      if (inside) {
-        float part[NCH];
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) part[c] = 0.0f;
-        const int e0 = max(dlo, c0), e1 = min(dhi, c1);
-        for (int d = e0; d <= e1; ++d) {
-          const BinLDS &e = sh.bins[d - c0];
-          const double2 nn = e.n;
-          const float4 w0 = e.w0;
-          const float w = chord_weight(nn.x, nn.y, w0.x, w0.y, w0.z, dx, dy);
-          float qv[9];
-          qv[0] = w0.w;
-          if (NCH > 1) {
-            const float4 w1 = e.w1;
-            qv[1] = w1.x; qv[2] = w1.y; qv[3] = w1.z; qv[4] = w1.w;
-          }
-          if (NCH > 5) {
-            const float4 w2 = e.w2;
-            qv[5] = w2.x; qv[6] = w2.y; qv[7] = w2.z; qv[8] = w2.w;
-          }
-#pragma unroll
-          for (int c = 0; c < NCH; ++c) part[c] = __fmaf_rn(w, qv[c], part[c]);
+      if (nbv > 0) {
+        const ViewGeom vg = sd.views[v];
+        int dlo = vt.d0, dhi = vt.d1;
+        if (vt.hw >= 0.0f) {
+          const float num = -vg.sb * X + vg.cb * Y;
+          const float den = sd.sid_px - vg.cb * X - vg.sb * Y;
+          const float t = num * __builtin_amdgcn_rcpf(den);
+          const float bc = __fmaf_rn(t, sd.bin_scale, sd.cbin);
+          dlo = max(dlo, (int)ceilf(bc - vt.hw));
+          dhi = min(dhi, (int)floorf(bc + vt.hw));
         }
+        const double dx = vg.sx - (double)ix;
+        const double dy = vg.sy - (double)iy;
+        if (nbv <= kBpMaxBins) {
+          if (inside) accumulate_bins<NCH>(sh.bins[cur], dlo - vt.d0, dhi - vt.d0, dx, dy, part);
+        } else {
+          // shadow wider than the staging buffer: chunks of bins, synchronously
+          for (int c0 = vt.d0; c0 <= vt.d1; c0 += kBpMaxBins) {
+            const int c1 = min(vt.d1, c0 + kBpMaxBins - 1);
+            __syncthreads();
+            if (tid <= c1 - c0) {
+              BinRegs<NCH> b;
+              bin_load<NCH>(sd, q, q_stride, v * nb + c0 + tid, b);
+              bin_store<NCH>(b, sh.bins[cur][tid]);
+            }
+            __syncthreads();
+            if (inside) accumulate_bins<NCH>(sh.bins[cur], max(dlo, c0) - c0, min(dhi, c1) - c0, dx, dy, part);
+          }
+        }
+      }
+      if (have_next) bin_store<NCH>(nxt, sh.bins[cur ^ 1][tid]);
+      if (++since_flush == kBpFlush) {
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) acc[c] += (double)part[c];
+        for (int c = 0; c < NCH; ++c) {
+          acc[c] += (double)part[c];
+          part[c] = 0.0f;
+        }
+        since_flush = 0;
       }
       __syncthreads();
     }
   }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) acc[c] += (double)part[c];
 }
 
 }  // namespace osscir

@@ -17,31 +17,36 @@ namespace osscir {
 
 // ----------------------------------------------------------------- packing
 //
-// Up to three planar channels -> two interleaved float4 images: pk_xy[iy][ix]
-// (rows contiguous) and pk_yx[ix][iy] (columns contiguous), through a
-// 32 x 32 LDS tile for the transposed writes.
+// Up to three planar channels -> two interleaved float4 images with a zero
+// border of kPad pixels: pk_xy[iy + kPad][ix + kPad] (rows contiguous) and
+// pk_yx[ix + kPad][iy + kPad] (columns contiguous), written through a 32 x 32
+// LDS tile for the transposed copy.  The border lets the forward projector
+// read its candidate pixels without bounds checks: a candidate outside the
+// image reads 0 and adds w * 0 = 0.
 __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ f, int n, int nch, float4 *__restrict__ pk_xy,
                                                float4 *__restrict__ pk_yx) {
   __shared__ float4 tile[32][33];
+  const int np = n + 2 * kPad;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;  // padded coordinates
   const size_t nn = (size_t)n * n;
   for (int r = ty; r < 32; r += 8) {
-    const int ix = bx + tx, iy = by + r;
+    const int px = bx + tx, py = by + r;
+    const int ix = px - kPad, iy = py - kPad;
     float4 val = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (ix < n && iy < n) {
+    if (ix >= 0 && ix < n && iy >= 0 && iy < n) {
       const size_t k = (size_t)iy * n + ix;
       val.x = f[k];
       if (nch > 1) val.y = f[nn + k];
       if (nch > 2) val.z = f[2 * nn + k];
-      pk_xy[k] = val;
     }
+    if (px < np && py < np) pk_xy[(size_t)py * np + px] = val;
     tile[r][tx] = val;
   }
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
-    const int iy = by + tx, ix = bx + r;
-    if (ix < n && iy < n) pk_yx[(size_t)ix * n + iy] = tile[tx][r];
+    const int py = by + tx, px = bx + r;
+    if (px < np && py < np) pk_yx[(size_t)px * np + py] = tile[tx][r];
   }
 }
 
@@ -56,7 +61,12 @@ __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ f, int n
 // read the column-contiguous packed image, rays walking rows the
 // row-contiguous one, so neighbouring lanes (neighbouring bins) read
 // neighbouring addresses; all lanes of a wave step through the same walk
-// index (the wave's union of walk ranges).
+// index (the wave's union of walk ranges), two columns per step with every
+// load issued before the weights are formed.
+//
+// The FP64 offsets from the source are formed exactly as the back-projector
+// forms them: s - (double)i for integer i is exact, so the offset of the
+// second candidate, (s - iv0) - 1, equals s - (iv0 + 1) bit for bit.
 __device__ __forceinline__ int wave_min(int x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
@@ -66,6 +76,68 @@ __device__ __forceinline__ int wave_max(int x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
   return x;
+}
+
+template <bool XMAJOR, bool THIRD, bool COUNT>
+__device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4 *__restrict__ img, double s_u,
+                                             double s_v, float slope, float base, const RayLine &ray, float &a0,
+                                             float &a1, float &a2) {
+  const int np = n + 2 * kPad;
+  constexpr int NC = THIRD ? 3 : 2;
+  for (int u = lo; u <= hi; u += 2) {
+    float4 fv[2][NC];
+    float w[2][NC];
+    int iv0s[2], ives[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int uu = u + k;
+      const float ys = __fmaf_rn(slope, (float)uu, base);
+      const float fl = floorf(ys);
+      const int iv0 = min(max((int)fl, -2), n);
+      const int ive = (ys - fl < 0.5f) ? iv0 - 1 : iv0 + 2;
+      iv0s[k] = iv0;
+      ives[k] = ive;
+      if (!COUNT) {
+        const float4 *__restrict__ line = img + (size_t)(uu + kPad) * np + kPad;
+        fv[k][0] = line[iv0];
+        fv[k][1] = line[iv0 + 1];
+        if (THIRD) fv[k][2] = line[ive];
+      }
+      const double du = s_u - (double)uu;
+      const double dv0 = s_v - (double)iv0;
+      const double dv1 = dv0 - 1.0;
+      if (XMAJOR) {
+        w[k][0] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, du, dv0);
+        w[k][1] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, du, dv1);
+      } else {
+        w[k][0] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, dv0, du);
+        w[k][1] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, dv1, du);
+      }
+      if (THIRD) {
+        const double dve = s_v - (double)ive;
+        w[k][2] = XMAJOR ? chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, du, dve)
+                         : chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, dve, du);
+      }
+      // a column index past the image reads the zero border; its weight is irrelevant
+      if (uu >= n) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) w[k][j] = 0.0f;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        if (COUNT) {
+          const int ivj = j == 0 ? iv0s[k] : (j == 1 ? iv0s[k] + 1 : ives[k]);
+          a0 += (w[k][j] > 0.0f && ivj >= 0 && ivj < n) ? 1.0f : 0.0f;
+        } else {
+          a0 = __fmaf_rn(w[k][j], fv[k][j].x, a0);
+          a1 = __fmaf_rn(w[k][j], fv[k][j].y, a1);
+          a2 = __fmaf_rn(w[k][j], fv[k][j].z, a2);
+        }
+      }
+  }
 }
 
 template <bool COUNT>
@@ -106,32 +178,19 @@ __global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__re
     }
   }
   const int lo = wave_min(iu_lo), hi = wave_max(iu_hi);
-  const float4 *__restrict__ img = xmajor ? pk_yx : pk_xy;
-  const double s_u = xmajor ? vg.sx : vg.sy;  // source along the walked axis
-  const double s_v = xmajor ? vg.sy : vg.sx;
-  const int ncand = near45 ? 3 : 2;
+  const bool any45 = __any(near45);
   float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-  for (int iu = lo; iu <= hi; ++iu) {
-    if (!active) continue;
-    const float ys = __fmaf_rn(slope, (float)iu, base);
-    const float fl = floorf(ys);
-    const int iv0 = (int)fl;
-    const int extra = (ys - fl < 0.5f) ? iv0 - 1 : iv0 + 2;
-    const double du = s_u - (double)iu;
-    const float4 *__restrict__ line = img + (size_t)iu * n;
-    for (int j = 0; j < ncand; ++j) {
-      const int iv = j == 0 ? iv0 : (j == 1 ? iv0 + 1 : extra);
-      if (iv < 0 || iv >= n) continue;
-      const double dv = s_v - (double)iv;
-      const float w = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, xmajor ? du : dv, xmajor ? dv : du);
-      if (COUNT) {
-        a0 += (w > 0.0f) ? 1.0f : 0.0f;
-      } else {
-        const float4 fv = line[iv];
-        a0 = __fmaf_rn(w, fv.x, a0);
-        a1 = __fmaf_rn(w, fv.y, a1);
-        a2 = __fmaf_rn(w, fv.z, a2);
-      }
+  if (active) {
+    if (xmajor) {
+      if (any45)
+        forward_walk<true, true, COUNT>(lo, hi, n, pk_yx, vg.sx, vg.sy, slope, base, ray, a0, a1, a2);
+      else
+        forward_walk<true, false, COUNT>(lo, hi, n, pk_yx, vg.sx, vg.sy, slope, base, ray, a0, a1, a2);
+    } else {
+      if (any45)
+        forward_walk<false, true, COUNT>(lo, hi, n, pk_xy, vg.sy, vg.sx, slope, base, ray, a0, a1, a2);
+      else
+        forward_walk<false, false, COUNT>(lo, hi, n, pk_xy, vg.sy, vg.sx, slope, base, ray, a0, a1, a2);
     }
   }
   if (!active) return;
@@ -163,13 +222,17 @@ __global__ void __launch_bounds__(256) k_back(ScanDesc sd, const float *__restri
 
 // ----------------------------------------------------------------- launchers
 
-size_t pack_scratch_bytes(const ScanDesc &sd) { return 2 * (size_t)sd.n * sd.n * sizeof(float4); }
+size_t pack_scratch_bytes(const ScanDesc &sd) {
+  const size_t np = (size_t)sd.n + 2 * kPad;
+  return 2 * np * np * sizeof(float4);
+}
 
 hipError_t launch_forward(const ScanDesc &sd, const float *f, int nch, float *p, void *pack, hipStream_t st) {
   const size_t fs = (size_t)sd.n * sd.n, ps = (size_t)sd.n_rays;
+  const size_t np = (size_t)sd.n + 2 * kPad;
   float4 *pk_xy = reinterpret_cast<float4 *>(pack);
-  float4 *pk_yx = pk_xy + fs;
-  const dim3 pgrid((sd.n + 31) / 32, (sd.n + 31) / 32);
+  float4 *pk_yx = pk_xy + np * np;
+  const dim3 pgrid((unsigned)((np + 31) / 32), (unsigned)((np + 31) / 32));
   const dim3 fgrid((sd.n_bins + 255) / 256, sd.n_views);
   for (int c0 = 0; c0 < nch; c0 += 3) {
     const int k = nch - c0 >= 3 ? 3 : nch - c0;
