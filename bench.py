@@ -64,10 +64,23 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", default="24,72", help="view-subset sizes of the oracle sample")
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 times) to calibrate HBM byte counters")
     return ap.parse_args()
 
 
-DEFAULT_LAM = {"tiny": 3e-7, "medium": 2e-7, "large": 4e-8}
+def copy_calibration(mib: int):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 3}), flush=True)
+
+
+DEFAULT_LAM = {"tiny": 3e-7, "medium": 3e-7, "large": 2e-8}
 
 
 def source_hash() -> str:
@@ -134,6 +147,9 @@ def main():
         print("bench.py measures one GPU: multi-GPU runs are not part of this build "
               "(slices shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import numpy as np
     import torch
 

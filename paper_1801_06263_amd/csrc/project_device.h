@@ -32,11 +32,15 @@ constexpr int kBpMaxBins = 128;   // bins staged per view; wider shadows take a 
 constexpr int kBpViewChunk = kBpThreads;
 constexpr int kBpFlush = 8;       // views summed in FP32 before the FP64 running sum
 
+// One staged bin.  The 80-byte stride (20 banks) puts the 16-byte pieces of
+// eight consecutive bins on 32 distinct LDS banks; a power-of-two stride
+// would fold them onto two bank groups.
 struct BinLDS {
   double2 n;   // nx, ny
   float4 w0;   // a, hmax, kappa, q0
   float4 w1;   // q1..q4
   float4 w2;   // q5..q8
+  float4 pad;
 };
 
 struct ViewTile {

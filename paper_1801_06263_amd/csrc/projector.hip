@@ -140,12 +140,28 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
   }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  The flat workgroup index is remapped so that XCD x processes a
+// contiguous range of (view, bin-chunk) items: an arc of views whose rays
+// mostly share one major axis, and hence one of the two packed copies.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ bool xcd_item(int nitems, int &item) {
+  const int b = blockIdx.x;
+  const int per = (nitems + kXcds - 1) / kXcds;
+  item = (b % kXcds) * per + b / kXcds;
+  return item < nitems;
+}
+
 template <bool COUNT>
 __global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__restrict__ pk_xy,
                                                   const float4 *__restrict__ pk_yx, float *__restrict__ p,
                                                   int p_stride, int nch) {
-  const int d = blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = blockIdx.y;
+  const int nchunk = (sd.n_bins + 255) / 256;
+  int item;
+  if (!xcd_item(sd.n_views * nchunk, item)) return;
+  const int v = item / nchunk;
+  const int d = (item - v * nchunk) * 256 + threadIdx.x;
   const int n = sd.n;
   const bool active = d < sd.n_bins;
   const ViewGeom vg = sd.views[v];
@@ -222,6 +238,11 @@ __global__ void __launch_bounds__(256) k_back(ScanDesc sd, const float *__restri
 
 // ----------------------------------------------------------------- launchers
 
+static unsigned forward_blocks(const ScanDesc &sd) {
+  const int items = sd.n_views * ((sd.n_bins + 255) / 256);
+  return (unsigned)(((items + kXcds - 1) / kXcds) * kXcds);
+}
+
 size_t pack_scratch_bytes(const ScanDesc &sd) {
   const size_t np = (size_t)sd.n + 2 * kPad;
   return 2 * np * np * sizeof(float4);
@@ -233,7 +254,7 @@ hipError_t launch_forward(const ScanDesc &sd, const float *f, int nch, float *p,
   float4 *pk_xy = reinterpret_cast<float4 *>(pack);
   float4 *pk_yx = pk_xy + np * np;
   const dim3 pgrid((unsigned)((np + 31) / 32), (unsigned)((np + 31) / 32));
-  const dim3 fgrid((sd.n_bins + 255) / 256, sd.n_views);
+  const dim3 fgrid(forward_blocks(sd));
   for (int c0 = 0; c0 < nch; c0 += 3) {
     const int k = nch - c0 >= 3 ? 3 : nch - c0;
     hipLaunchKernelGGL(k_pack, pgrid, dim3(256), 0, st, f + c0 * fs, sd.n, k, pk_xy, pk_yx);
@@ -247,7 +268,7 @@ hipError_t launch_forward(const ScanDesc &sd, const float *f, int nch, float *p,
 }
 
 hipError_t launch_count(const ScanDesc &sd, int *nnz, hipStream_t st) {
-  const dim3 fgrid((sd.n_bins + 255) / 256, sd.n_views);
+  const dim3 fgrid(forward_blocks(sd));
   hipLaunchKernelGGL(k_forward<true>, fgrid, dim3(256), 0, st, sd, nullptr, nullptr, reinterpret_cast<float *>(nnz),
                      0, 1);
   return hipGetLastError();
