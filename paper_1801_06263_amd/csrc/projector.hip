@@ -78,12 +78,16 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
+// Products are summed in FP32 over 16 columns at a time, then into an FP64
+// running sum (a ray crosses up to thousands of pixels).
 template <bool XMAJOR, bool THIRD, bool COUNT>
 __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4 *__restrict__ img, double s_u,
-                                             double s_v, float slope, float base, const RayLine &ray, float &a0,
-                                             float &a1, float &a2) {
+                                             double s_v, float slope, float base, const RayLine &ray, double &s0,
+                                             double &s1, double &s2) {
   const int np = n + 2 * kPad;
   constexpr int NC = THIRD ? 3 : 2;
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+  int pairs = 0;
   for (int u = lo; u <= hi; u += 2) {
     float4 fv[2][NC];
     float w[2][NC];
@@ -137,7 +141,17 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
           a2 = __fmaf_rn(w[k][j], fv[k][j].z, a2);
         }
       }
+    if (++pairs == 8) {
+      s0 += (double)a0;
+      s1 += (double)a1;
+      s2 += (double)a2;
+      a0 = a1 = a2 = 0.0f;
+      pairs = 0;
+    }
   }
+  s0 += (double)a0;
+  s1 += (double)a1;
+  s2 += (double)a2;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
@@ -195,7 +209,7 @@ __global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__re
   }
   const int lo = wave_min(iu_lo), hi = wave_max(iu_hi);
   const bool any45 = __any(near45);
-  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (active) {
     if (xmajor) {
       if (any45)
@@ -215,9 +229,9 @@ __global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__re
     reinterpret_cast<int *>(p)[l] = (int)a0;
     return;
   }
-  p[l] = a0;
-  if (nch > 1) p[p_stride + l] = a1;
-  if (nch > 2) p[2 * p_stride + l] = a2;
+  p[l] = (float)a0;
+  if (nch > 1) p[p_stride + l] = (float)a1;
+  if (nch > 2) p[2 * p_stride + l] = (float)a2;
 }
 
 // ----------------------------------------------------------------- back

@@ -17,3 +17,28 @@ def rotation(seed=0):
     rng = np.random.default_rng(seed)
     q, r = np.linalg.qr(rng.standard_normal((3, 3)))
     return q * np.sign(np.diag(r))[None, :]
+
+
+def dev(a):
+    """numpy -> float32 CUDA tensor."""
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    """CUDA tensor -> float64 numpy (synchronising)."""
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def normwise(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def sino(a_lw, n_views, n_bins):
+    """oracle ray-major [L, W] -> library [W, V, D]."""
+    return np.ascontiguousarray(np.asarray(a_lw).T.reshape(-1, n_views, n_bins))
+
+
+UPPER = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
