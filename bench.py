@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--workload", default="large", choices=["tiny", "medium", "large"])
     ap.add_argument("--precond", default="block", choices=["block", "diag"])
     ap.add_argument("--curvature", default="clip", choices=["clip", "window"])
-    ap.add_argument("--fp64-small", type=int, default=0)
+    ap.add_argument("--fp64-small", type=int, default=1)
     ap.add_argument("--lam", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", default="24,72", help="view-subset sizes of the oracle sample")
