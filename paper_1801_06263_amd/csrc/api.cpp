@@ -14,6 +14,7 @@
 #include "kernels.h"
 #include "osscir.h"
 #include "projector.h"
+#include "project_device.h"
 #include "spectral.h"
 
 using namespace osscir;
@@ -211,6 +212,31 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   sd.bin_scale = (float)(g.sdd_cm / g.bin_cm);
   sd.cbin = 0.5f * (float)(D - 1);
   for (int w = 0; w < kWin; ++w) sd.n0[w] = (float)spec->n0[w];
+  // does any 16x16 tile's shadow exceed the back-projector's staging buffer?
+  // (the same corner projection the kernel uses, in FP64 with a margin)
+  sd.bp_wide = 0;
+  {
+    const int nt = (N + kBpTile - 1) / kBpTile;
+    for (int v = 0; v < V && !sd.bp_wide; ++v) {
+      const double cb = views[v].cb, sb = views[v].sb;
+      for (int ty = 0; ty < nt && !sd.bp_wide; ++ty)
+        for (int tx = 0; tx < nt; ++tx) {
+          double lo = 1e300, hi = -1e300;
+          for (int k = 0; k < 4; ++k) {
+            const double X = tx * kBpTile - c0 - 0.5 + ((k & 1) ? kBpTile : 0);
+            const double Y = ty * kBpTile - c0 - 0.5 + ((k & 2) ? kBpTile : 0);
+            const double t = (-sb * X + cb * Y) / (g.sid_cm / h - cb * X - sb * Y);
+            lo = std::min(lo, t);
+            hi = std::max(hi, t);
+          }
+          const double span = (hi - lo) * (g.sdd_cm / g.bin_cm) + 3.0;
+          if (span > kBpMaxBins - 2) {
+            sd.bp_wide = 1;
+            break;
+          }
+        }
+    }
+  }
   sd.rays = p->d_rays;
   sd.views = p->d_views;
   sd.rho = p->d_rho;

@@ -44,6 +44,7 @@ struct ScanDesc {
   float bin_scale;   // sdd / bin pitch (bins per unit tan)
   float cbin;        // (n_bins - 1) / 2
   float n0[kWin];    // incident counts per window
+  int bp_wide;       // some 16x16-tile shadow exceeds the back-projector's staging buffer
   const struct RayLine *rays;  // [L]
   const ViewGeom *views;        // [V]
   const float *rho;     // [L]

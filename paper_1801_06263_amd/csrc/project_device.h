@@ -7,9 +7,9 @@
 // projects the tile's four corners onto the detector: every ray that meets
 // the tile has its bin inside that shadow (+0.05 bin), and the same corners
 // bound the half-width of every pixel's own shadow in that view.  The bins of
-// a view (line parameters and the NCH input values) are staged in LDS; the
-// loads of view v+1 are issued before view v is processed and stored after,
-// so each view costs one barrier.  Each thread then projects its pixel centre
+// a view (line parameters and the NCH input values) are staged in LDS by all
+// four waves; the loads of view v+1 are issued before view v is processed and
+// stored after, so each view costs one barrier.  Each thread then projects its pixel centre
 // (one reciprocal), takes the bins within the bounded half-width (+0.02 bin)
 // and accumulates w * q.
 //
@@ -94,10 +94,18 @@ struct BinRegs {
   float q[NCH];
 };
 
+// Staged bins are spread over the workgroup's four waves in runs of 16
+// consecutive bins (lanes 0..15 of each wave, then 16..31, ...), so the
+// staging work of a view is shared while loads and LDS stores stay
+// contiguous.
+__device__ __forceinline__ int stage_bin_of_thread(int tid) {
+  return ((tid & 63) >> 4) * 64 + (tid >> 6) * 16 + (tid & 15);
+}
+
 template <int NCH>
-__device__ __forceinline__ void bin_load(const ScanDesc &sd, const float *__restrict__ q, int q_stride, int l,
-                                         BinRegs<NCH> &b) {
-  b.r = sd.rays[l];
+__device__ __forceinline__ void bin_load(const RayLine *__restrict__ rays, const float *__restrict__ q,
+                                         unsigned q_stride, unsigned l, BinRegs<NCH> &b) {
+  b.r = rays[l];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) b.q[c] = q[c * q_stride + l];
 }
@@ -114,120 +122,127 @@ __device__ __forceinline__ void bin_store(const BinRegs<NCH> &b, BinLDS &e) {
 }
 
 template <int NCH>
+__device__ __forceinline__ void accumulate_bin(const BinLDS &e, double dx, double dy, float part[NCH]) {
+  const double2 nn = e.n;
+  const float4 w0 = e.w0;
+  const float w = chord_weight(nn.x, nn.y, w0.x, w0.y, w0.z, dx, dy);
+  float qv[9];
+  qv[0] = w0.w;
+  if (NCH > 1) {
+    const float4 w1 = e.w1;
+    qv[1] = w1.x; qv[2] = w1.y; qv[3] = w1.z; qv[4] = w1.w;
+  }
+  if (NCH > 5) {
+    const float4 w2 = e.w2;
+    qv[5] = w2.x; qv[6] = w2.y; qv[7] = w2.z; qv[8] = w2.w;
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) part[c] = __fmaf_rn(w, qv[c], part[c]);
+}
+
+// bins b0..b1 of the staged view (b0 > b1: none); the first two unrolled
+template <int NCH>
 __device__ __forceinline__ void accumulate_bins(const BinLDS *__restrict__ bins, int b0, int b1, double dx, double dy,
                                                 float part[NCH]) {
-  for (int b = b0; b <= b1; ++b) {
-    const BinLDS &e = bins[b];
-    const double2 nn = e.n;
-    const float4 w0 = e.w0;
-    const float w = chord_weight(nn.x, nn.y, w0.x, w0.y, w0.z, dx, dy);
-    float qv[9];
-    qv[0] = w0.w;
-    if (NCH > 1) {
-      const float4 w1 = e.w1;
-      qv[1] = w1.x; qv[2] = w1.y; qv[3] = w1.z; qv[4] = w1.w;
-    }
-    if (NCH > 5) {
-      const float4 w2 = e.w2;
-      qv[5] = w2.x; qv[6] = w2.y; qv[7] = w2.z; qv[8] = w2.w;
-    }
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) part[c] = __fmaf_rn(w, qv[c], part[c]);
+  if (b0 <= b1) accumulate_bin<NCH>(bins[b0], dx, dy, part);
+  if (b0 + 1 <= b1) accumulate_bin<NCH>(bins[b0 + 1], dx, dy, part);
+  for (int b = b0 + 2; b <= b1; ++b) accumulate_bin<NCH>(bins[b], dx, dy, part);
+}
+
+// Bins of pixel (X, Y) (centred coordinates) in view vg: the tile's range
+// [d0, d1] narrowed to the pixel's bounded shadow.
+__device__ __forceinline__ void pixel_bins(const ScanDesc &sd, const ViewGeom &vg, const ViewTile &vt, float X,
+                                           float Y, int &dlo, int &dhi) {
+  dlo = vt.d0;
+  dhi = vt.d1;
+  if (vt.hw >= 0.0f) {
+    const float num = __fmaf_rn(vg.cb, Y, -vg.sb * X);
+    const float den = __fmaf_rn(-vg.sb, Y, __fmaf_rn(-vg.cb, X, sd.sid_px));
+    const float bc = __fmaf_rn(num * __builtin_amdgcn_rcpf(den), sd.bin_scale, sd.cbin);
+    dlo = max(dlo, (int)ceilf(bc - vt.hw));
+    dhi = min(dhi, (int)floorf(bc + vt.hw));
   }
 }
 
-template <int NCH>
+// WIDE: some tile shadow may exceed kBpMaxBins bins; such views are staged
+// and accumulated in chunks with extra barriers.  The plan selects the
+// variant from the geometry, so the common case carries no chunk logic.
+template <int NCH, bool WIDE>
 __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, int tile_y, const float *__restrict__ q,
-                                                int q_stride, double acc[NCH], BpShared &sh) {
+                                                int q_stride_i, double acc[NCH], BpShared &sh) {
   static_assert(NCH >= 1 && NCH <= 9, "1..9 channels");
   const int tid = threadIdx.x;
   const int ix = tile_x * kBpTile + (tid & (kBpTile - 1));
   const int iy = tile_y * kBpTile + (tid / kBpTile);
-  const int n = sd.n, nb = sd.n_bins, V = sd.n_views;
+  const int n = sd.n, V = sd.n_views;
+  const unsigned nb = (unsigned)sd.n_bins, q_stride = (unsigned)q_stride_i;
+  const RayLine *__restrict__ rays = sd.rays;
   const bool inside = ix < n && iy < n;
   const float X = (float)ix - sd.c0;  // centred, for the detector projection
   const float Y = (float)iy - sd.c0;
-  float part[NCH];
+  const double fx = (double)ix, fy = (double)iy;
+  const int sb = stage_bin_of_thread(tid);
 #pragma unroll
-  for (int c = 0; c < NCH; ++c) {
-    acc[c] = 0.0;
-    part[c] = 0.0f;
-  }
-  int since_flush = 0;
+  for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
   for (int vc = 0; vc < V; vc += kBpViewChunk) {
     const int cnt = min(kBpViewChunk, V - vc);
-    __syncthreads();  // the previous chunk's last view is done with sh
+    __syncthreads();  // the previous chunk is done with sh
     if (tid < cnt) tile_view_bounds(sd, sd.views[vc + tid], tile_x, tile_y, sh.vt[tid]);
     __syncthreads();
-    // stage the chunk's first view
     {
       const ViewTile vt = sh.vt[0];
-      const int nbv = vt.d1 - vt.d0 + 1;
-      if (nbv <= kBpMaxBins && tid < nbv) {
+      if (vt.d1 - vt.d0 + 1 <= kBpMaxBins && sb <= vt.d1 - vt.d0) {
         BinRegs<NCH> b;
-        bin_load<NCH>(sd, q, q_stride, vc * nb + vt.d0 + tid, b);
-        bin_store<NCH>(b, sh.bins[0][tid]);
+        bin_load<NCH>(rays, q, q_stride, (unsigned)vc * nb + (unsigned)(vt.d0 + sb), b);
+        bin_store<NCH>(b, sh.bins[0][sb]);
       }
     }
     __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
-      const int v = vc + j;
-      const int cur = j & 1;
-      const ViewTile vt = sh.vt[j];
-      const int nbv = vt.d1 - vt.d0 + 1;
-      // issue the next view's loads
-      BinRegs<NCH> nxt;
-      bool have_next = false;
-      if (j + 1 < cnt) {
-        const ViewTile vn = sh.vt[j + 1];
-        const int nbn = vn.d1 - vn.d0 + 1;
-        have_next = nbn <= kBpMaxBins && tid < nbn;
-        if (have_next) bin_load<NCH>(sd, q, q_stride, (v + 1) * nb + vn.d0 + tid, nxt);
-      }
-      if (nbv > 0) {
-        const ViewGeom vg = sd.views[v];
-        int dlo = vt.d0, dhi = vt.d1;
-        if (vt.hw >= 0.0f) {
-          const float num = -vg.sb * X + vg.cb * Y;
-          const float den = sd.sid_px - vg.cb * X - vg.sb * Y;
-          const float t = num * __builtin_amdgcn_rcpf(den);
-          const float bc = __fmaf_rn(t, sd.bin_scale, sd.cbin);
-          dlo = max(dlo, (int)ceilf(bc - vt.hw));
-          dhi = min(dhi, (int)floorf(bc + vt.hw));
+    for (int j0 = 0; j0 < cnt; j0 += kBpFlush) {
+      float part[NCH];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) part[c] = 0.0f;
+      const int jend = min(cnt, j0 + kBpFlush);
+      for (int j = j0; j < jend; ++j) {
+        const int v = vc + j;
+        const int cur = j & 1;
+        const ViewTile vt = sh.vt[j];
+        // issue the next view's loads
+        BinRegs<NCH> nxt;
+        bool have_next = false;
+        if (j + 1 < cnt) {
+          const ViewTile vn = sh.vt[j + 1];
+          have_next = (!WIDE || vn.d1 - vn.d0 + 1 <= kBpMaxBins) && sb <= vn.d1 - vn.d0;
+          if (have_next) bin_load<NCH>(rays, q, q_stride, (unsigned)(v + 1) * nb + (unsigned)(vn.d0 + sb), nxt);
         }
-        const double dx = vg.sx - (double)ix;
-        const double dy = vg.sy - (double)iy;
-        if (nbv <= kBpMaxBins) {
-          if (inside) accumulate_bins<NCH>(sh.bins[cur], dlo - vt.d0, dhi - vt.d0, dx, dy, part);
+        const ViewGeom vg = sd.views[v];
+        int dlo, dhi;
+        pixel_bins(sd, vg, vt, X, Y, dlo, dhi);
+        const double dx = vg.sx - fx;
+        const double dy = vg.sy - fy;
+        if (!WIDE || vt.d1 - vt.d0 + 1 <= kBpMaxBins) {
+          // (the plan guarantees d1 - d0 < kBpMaxBins here; the min keeps reads in the buffer regardless)
+          if (inside) accumulate_bins<NCH>(sh.bins[cur], dlo - vt.d0, min(dhi - vt.d0, kBpMaxBins - 1), dx, dy, part);
         } else {
-          // shadow wider than the staging buffer: chunks of bins, synchronously
           for (int c0 = vt.d0; c0 <= vt.d1; c0 += kBpMaxBins) {
             const int c1 = min(vt.d1, c0 + kBpMaxBins - 1);
             __syncthreads();
-            if (tid <= c1 - c0) {
+            if (sb <= c1 - c0) {
               BinRegs<NCH> b;
-              bin_load<NCH>(sd, q, q_stride, v * nb + c0 + tid, b);
-              bin_store<NCH>(b, sh.bins[cur][tid]);
+              bin_load<NCH>(rays, q, q_stride, (unsigned)v * nb + (unsigned)(c0 + sb), b);
+              bin_store<NCH>(b, sh.bins[cur][sb]);
             }
             __syncthreads();
             if (inside) accumulate_bins<NCH>(sh.bins[cur], max(dlo, c0) - c0, min(dhi, c1) - c0, dx, dy, part);
           }
         }
+        if (have_next) bin_store<NCH>(nxt, sh.bins[cur ^ 1][sb]);
+        __syncthreads();
       }
-      if (have_next) bin_store<NCH>(nxt, sh.bins[cur ^ 1][tid]);
-      if (++since_flush == kBpFlush) {
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          acc[c] += (double)part[c];
-          part[c] = 0.0f;
-        }
-        since_flush = 0;
-      }
-      __syncthreads();
+      for (int c = 0; c < NCH; ++c) acc[c] += (double)part[c];
     }
   }
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) acc[c] += (double)part[c];
 }
 
 }  // namespace osscir

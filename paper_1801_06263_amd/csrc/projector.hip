@@ -61,8 +61,8 @@ __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ f, int n
 // read the column-contiguous packed image, rays walking rows the
 // row-contiguous one, so neighbouring lanes (neighbouring bins) read
 // neighbouring addresses; all lanes of a wave step through the same walk
-// index (the wave's union of walk ranges), two columns per step with every
-// load issued before the weights are formed.
+// index (the wave's union of walk ranges), several columns per step with
+// every load issued before the weights are formed.
 //
 // The FP64 offsets from the source are formed exactly as the back-projector
 // forms them: s - (double)i for integer i is exact, so the offset of the
@@ -79,7 +79,11 @@ __device__ __forceinline__ int wave_max(int x) {
 }
 
 // Products are summed in FP32 over 16 columns at a time, then into an FP64
-// running sum (a ray crosses up to thousands of pixels).
+// running sum (a ray crosses up to thousands of pixels).  kFpUnroll columns
+// are processed per step; the last step may run past the image by up to
+// kFpUnroll - 1 columns, which the zero border (kPad >= kFpUnroll) absorbs.
+constexpr int kFpUnroll = 4;
+static_assert(kPad >= kFpUnroll, "border must cover the unrolled tail");
 template <bool XMAJOR, bool THIRD, bool COUNT>
 __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4 *__restrict__ img, double s_u,
                                              double s_v, float slope, float base, const RayLine &ray, double &s0,
@@ -88,12 +92,12 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
   constexpr int NC = THIRD ? 3 : 2;
   float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
   int pairs = 0;
-  for (int u = lo; u <= hi; u += 2) {
-    float4 fv[2][NC];
-    float w[2][NC];
-    int iv0s[2], ives[2];
+  for (int u = lo; u <= hi; u += kFpUnroll) {
+    float4 fv[kFpUnroll][NC];
+    float w[kFpUnroll][NC];
+    int iv0s[kFpUnroll], ives[kFpUnroll];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kFpUnroll; ++k) {
       const int uu = u + k;
       const float ys = __fmaf_rn(slope, (float)uu, base);
       const float fl = floorf(ys);
@@ -129,7 +133,7 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
       }
     }
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < kFpUnroll; ++k)
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         if (COUNT) {
@@ -141,7 +145,7 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
           a2 = __fmaf_rn(w[k][j], fv[k][j].z, a2);
         }
       }
-    if (++pairs == 8) {
+    if (++pairs == 16 / kFpUnroll) {
       s0 += (double)a0;
       s1 += (double)a1;
       s2 += (double)a2;
@@ -236,12 +240,12 @@ __global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__re
 
 // ----------------------------------------------------------------- back
 
-template <int NCH>
+template <int NCH, bool WIDE>
 __global__ void __launch_bounds__(256) k_back(ScanDesc sd, const float *__restrict__ q, int q_stride,
                                                float *__restrict__ b, int b_stride) {
   __shared__ BpShared sh;
   double acc[NCH];
-  back_accumulate<NCH>(sd, blockIdx.x, blockIdx.y, q, q_stride, acc, sh);
+  back_accumulate<NCH, WIDE>(sd, blockIdx.x, blockIdx.y, q, q_stride, acc, sh);
   const int ix = blockIdx.x * kBpTile + (threadIdx.x & (kBpTile - 1));
   const int iy = blockIdx.y * kBpTile + (threadIdx.x / kBpTile);
   if (ix >= sd.n || iy >= sd.n) return;
@@ -292,7 +296,10 @@ template <int NCH>
 static hipError_t launch_back_n(const ScanDesc &sd, const float *q, int q_stride, float *b, int b_stride,
                                 hipStream_t st) {
   const dim3 grid((sd.n + kBpTile - 1) / kBpTile, (sd.n + kBpTile - 1) / kBpTile);
-  hipLaunchKernelGGL(k_back<NCH>, grid, dim3(kBpTile * kBpTile), 0, st, sd, q, q_stride, b, b_stride);
+  if (sd.bp_wide)
+    hipLaunchKernelGGL((k_back<NCH, true>), grid, dim3(kBpTile * kBpTile), 0, st, sd, q, q_stride, b, b_stride);
+  else
+    hipLaunchKernelGGL((k_back<NCH, false>), grid, dim3(kBpTile * kBpTile), 0, st, sd, q, q_stride, b, b_stride);
   return hipGetLastError();
 }
 

@@ -339,13 +339,13 @@ __global__ void k_scale_steps(int count, float lambda, float *__restrict__ v) {
 //                 diag   f'_m = f_m - lambda (sum_l X q_l)_m / (sum_l X h_l)_m
 //                 fbar'  = 2 f' - f.
 // The 3x3 solve takes the FP64 sums directly (equilibrated Cholesky).
-template <bool BLOCK>
+template <bool BLOCK, bool WIDE>
 __global__ void __launch_bounds__(256) k_back_primal(ScanDesc sd, const float *__restrict__ qS,
                                                       float *__restrict__ f, float *__restrict__ fbar, float lambda) {
   __shared__ BpShared sh;
   constexpr int NCH = BLOCK ? 9 : 6;
   double acc[NCH];
-  back_accumulate<NCH>(sd, blockIdx.x, blockIdx.y, qS, sd.n_rays, acc, sh);
+  back_accumulate<NCH, WIDE>(sd, blockIdx.x, blockIdx.y, qS, sd.n_rays, acc, sh);
   const int ix = blockIdx.x * kBpTile + (threadIdx.x & (kBpTile - 1));
   const int iy = blockIdx.y * kBpTile + (threadIdx.x / kBpTile);
   if (ix >= sd.n || iy >= sd.n) return;
@@ -452,10 +452,13 @@ hipError_t launch_spectral_dual(const ScanDesc &sd, const float *p, const float 
 hipError_t launch_back_primal(const ScanDesc &sd, const float *qS, float *f, float *fbar, float lambda, bool block,
                               bool fp64, hipStream_t st) {
   (void)fp64;
-  if (block)
-    hipLaunchKernelGGL((k_back_primal<true>), pix_grid(sd), dim3(256), 0, st, sd, qS, f, fbar, lambda);
-  else
-    hipLaunchKernelGGL((k_back_primal<false>), pix_grid(sd), dim3(256), 0, st, sd, qS, f, fbar, lambda);
+#define OSSCIR_BP(B, W) hipLaunchKernelGGL((k_back_primal<B, W>), pix_grid(sd), dim3(256), 0, st, sd, qS, f, fbar, lambda)
+  if (block) {
+    if (sd.bp_wide) OSSCIR_BP(true, true); else OSSCIR_BP(true, false);
+  } else {
+    if (sd.bp_wide) OSSCIR_BP(false, true); else OSSCIR_BP(false, false);
+  }
+#undef OSSCIR_BP
   return hipGetLastError();
 }
 
