@@ -18,9 +18,11 @@
  *    (allocated on the device the plan was created on), unless documented
  *    "host".  The library allocates device memory only inside
  *    osscir_plan_create (its constant tables, ray geometry and a 32 (n+8)^2-byte
- *    image scratch used by osscir_forward_project) and frees it in
- *    osscir_plan_destroy; it keeps no pointer to caller memory after a call
- *    returns.
+ *    image scratch used by osscir_forward_project), freed in
+ *    osscir_plan_destroy, and inside the batch calls (osscir_batch_*: slot
+ *    table, work lists, per-tile sums, the tuner's snapshot), freed in
+ *    osscir_batch_destroy.  Apart from a batch's bound slots it keeps no
+ *    pointer to caller memory after a call returns.
  *  - Calls that take a stream enqueue their work asynchronously on it (NULL =
  *    the null stream) and return without synchronising.  Only
  *    osscir_plan_create and osscir_plan_destroy synchronise.
@@ -198,6 +200,84 @@ int osscir_ray_nnz(osscir_plan plan, int32_t *nnz, osscir_stream stream);
  * in a fixed order, written to the DEVICE double *out.  Needs work. */
 int osscir_dtpl(osscir_plan plan, const float *f, const float *c, double *out, void *work, size_t work_bytes,
                 osscir_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Batched iterations: many independent scans ("slots", each with its own
+ * plan, state and lambda) advanced together, one launch per stage for the
+ * whole batch (forward projection, spectral model + dual step,
+ * back-projection + primal step, end-of-iteration bookkeeping).  Each slot
+ * follows exactly the trajectory osscir_mocca_iterate gives its scan alone
+ * (bit for bit, whatever the other slots and the launch configuration); its
+ * iteration is the one of Sec. II, unchanged.
+ *
+ * A slot stops by itself once it has run max_iter iterations (if > 0) or
+ * once the relative change ||f_{n+1} - f_n||_2 / ||f_{n+1}||_2 (FP64, over
+ * the three maps) is <= tol (if > 0); a stopped slot keeps its last iterate
+ * and costs nothing further.  A batch is used from one host thread, with one
+ * stream for all its calls.  Batch calls synchronise where stated.
+ * ------------------------------------------------------------------------ */
+typedef struct osscir_batch_s *osscir_batch;
+
+#define OSSCIR_SLOT_EMPTY 0
+#define OSSCIR_SLOT_RUNNING 1
+#define OSSCIR_SLOT_DONE 2
+
+typedef struct {
+  int32_t state;      /* OSSCIR_SLOT_* */
+  int32_t iters;      /* iterations run since the slot was bound */
+  double rel_change;  /* relative change of f in the last iteration */
+} osscir_slot_status;
+
+/* Launch configuration of the batched kernels (results do not depend on it):
+ * rays per workgroup of the forward and spectral kernels (64, 128 or 256),
+ * workgroups of each kernel (a multiple of 8, 8..65536; each workgroup walks
+ * its XCD's share of the work list), and whether work is split over the 8
+ * XCDs in contiguous cost-balanced ranges (1) or dealt round-robin (0). */
+typedef struct {
+  int32_t fp_rays, fp_wgs, fp_xcd;
+  int32_t spec_rays, spec_wgs, spec_xcd;
+  int32_t bp_wgs, bp_xcd;
+} osscir_batch_config;
+
+/* Create a batch of up to max_slots (1..256) slots on the current device.
+ * modes supplies precond, curvature and fp64_small for every slot (its lambda
+ * is ignored).  *out is NULL on failure. */
+int osscir_batch_create(const osscir_params *modes, int32_t max_slots, osscir_batch *out);
+/* Synchronises the device and frees the batch (not the plans or states). */
+int osscir_batch_destroy(osscir_batch batch);
+
+/* Bind scan `plan` with caller state `state` (as for osscir_mocca_iterate;
+ * its buffers must stay allocated until the slot is cleared or rebound) and
+ * step ratio lambda to slot `slot`, replacing what was bound there, with the
+ * stopping rule (max_iter, tol).  Enqueues the packing of state->fbar on
+ * stream; the slot starts running with the next osscir_batch_iterate.  The
+ * plan must outlive the binding. */
+int osscir_batch_set_slot(osscir_batch batch, int32_t slot, osscir_plan plan, const osscir_state *state,
+                          double lambda, int32_t max_iter, double tol, osscir_stream stream);
+/* Unbind a slot (state becomes OSSCIR_SLOT_EMPTY). */
+int osscir_batch_clear_slot(osscir_batch batch, int32_t slot);
+
+/* n_iter batched iterations of every running slot.  use_graph = 1 replays a
+ * captured HIP graph of one iteration (captured on first use and again after
+ * the work lists outgrow their buffers or the configuration changes);
+ * 0 launches the kernels directly.  Asynchronous, except that it may wait for
+ * its own earlier uploads before refilling the host staging buffers. */
+int osscir_batch_iterate(osscir_batch batch, int32_t n_iter, int32_t use_graph, osscir_stream stream);
+
+/* Status of every slot into the HOST array out[max_slots].  Synchronises the
+ * stream. */
+int osscir_batch_status(osscir_batch batch, osscir_slot_status *out, osscir_stream stream);
+
+int osscir_batch_get_config(osscir_batch batch, osscir_batch_config *cfg);
+int osscir_batch_set_config(osscir_batch batch, const osscir_batch_config *cfg);
+
+/* Autotuner: times candidate configurations of each stage on the bound
+ * slots (iters_per_trial timed iterations after one warm-up per candidate),
+ * keeps the fastest per stage, and restores every slot's f, fbar, y and
+ * status afterwards, so tuning leaves the trajectories unchanged.
+ * Synchronises.  The chosen configuration is returned in *cfg (may be
+ * NULL). */
+int osscir_batch_tune(osscir_batch batch, int32_t iters_per_trial, osscir_batch_config *cfg, osscir_stream stream);
 
 /* Thread-local description of the last error ("" if none). */
 const char *osscir_last_error(void);

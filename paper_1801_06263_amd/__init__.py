@@ -4,4 +4,4 @@ block-diagonal step preconditioning (arXiv 1801.06263).
 The compute path is the HIP library libosscir.so (C ABI in include/osscir.h);
 ``paper_1801_06263_amd.osscir`` is its thin binding.
 """
-from .osscir import Params, Plan, State, load_library, version  # noqa: F401
+from .osscir import Batch, Params, Plan, State, load_library, version  # noqa: F401

@@ -13,27 +13,18 @@
 #include "device_math.h"
 #include "kernels.h"
 #include "osscir.h"
+#include "plan.h"
 #include "projector.h"
 #include "project_device.h"
 #include "spectral.h"
 
 using namespace osscir;
 
-struct osscir_plan_s {
-  int device = -1;
-  ScanDesc sd{};
-  RayLine *d_rays = nullptr;
-  ViewGeom *d_views = nullptr;
-  void *d_pack = nullptr;  // packed-image scratch of the standalone projector calls
-  float *d_rho = nullptr;
-  float *d_tab = nullptr;
-};
-
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-int fail(int code, const char *fmt, ...) {
+int osscir::fail(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -43,25 +34,13 @@ int fail(int code, const char *fmt, ...) {
   return code;
 }
 
-int hip_fail(hipError_t e, const char *what) {
+int osscir::hip_fail(hipError_t e, const char *what) {
   return fail(OSSCIR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define OSSCIR_HIP(call, what)                   \
-  do {                                           \
-    hipError_t e_ = (call);                      \
-    if (e_ != hipSuccess) return hip_fail(e_, what); \
-  } while (0)
+void osscir::clear_error() { g_last_error.clear(); }
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// workspace regions: p [3][L] f32 | qS [9][L] f32 | partial sums (f64) |
-// packed images of the forward projector
-struct WorkLayout {
-  size_t p = 0, qS = 0, partial = 0, pack = 0, total = 0;
-};
-
-WorkLayout work_layout(const ScanDesc &sd) {
+WorkLayout osscir::work_layout(const ScanDesc &sd) {
   WorkLayout w;
   const size_t L = (size_t)sd.n_rays;
   w.p = 0;
@@ -72,13 +51,15 @@ WorkLayout work_layout(const ScanDesc &sd) {
   return w;
 }
 
-int check_plan(osscir_plan plan) {
+int osscir::check_plan(osscir_plan plan) {
   if (!plan) return fail(OSSCIR_EINVAL, "null plan");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
     return fail(OSSCIR_EINVAL, "plan was created on device %d, current device is %d", plan->device, dev);
   return OSSCIR_OK;
 }
+
+namespace {
 
 void free_plan(osscir_plan p) {
   if (!p) return;

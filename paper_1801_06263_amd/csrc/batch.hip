@@ -1,0 +1,154 @@
+// Batched MOCCA kernels: one launch per stage advances every running slot.
+//
+// Each kernel walks a host-built work list (forward: one view's chunk of
+// rays; spectral: a range of rays; back-projection: a 16 x 16 pixel tile)
+// with a fixed number of workgroups, so the launch shapes do not depend on
+// which scans are bound and one captured graph serves any mix.  The work of
+// an item is the single-scan device function of the same stage, so a slot
+// computes bit for bit what the single-scan path computes for its scan: the
+// forward walk of a wave depends only on the 64 bins it holds (chunks start
+// at multiples of 64), and the per-pixel sums run over views in order.
+#include "batch.h"
+#include "device_math.h"
+#include "forward_device.h"
+#include "kernels.h"
+#include "project_device.h"
+#include "spectral_device.h"
+
+namespace osscir {
+
+__device__ __forceinline__ int list_count(const WorkList &wl, int x) { return wl.buf[x]; }
+__device__ __forceinline__ int list_item(const WorkList &wl, int x, int j) {
+  return wl.buf[kListHeader + x * wl.cap + j];
+}
+
+__global__ void __launch_bounds__(256) kb_forward(const SlotDesc *__restrict__ slots,
+                                                   const SlotStatus *__restrict__ status, WorkList wl) {
+  const int x = blockIdx.x % kXcds;
+  const int stride = gridDim.x / kXcds;
+  const int cnt = list_count(wl, x);
+  const int R = blockDim.x;
+  for (int j = blockIdx.x / kXcds; j < cnt; j += stride) {
+    const int it = list_item(wl, x, j);
+    const int s = it >> kItemSlotShift, local = it & kItemLocalMask;
+    if (status[s].state != kSlotRunning) continue;
+    const SlotDesc &sl = slots[s];
+    const int nchunk = (sl.sd.n_bins + R - 1) / R;
+    const int v = local / nchunk;
+    forward_rays<false>(sl.sd, sl.pk_xy, sl.pk_yx, sl.p, sl.sd.n_rays, 3, v, (local - v * nchunk) * R);
+  }
+}
+
+template <typename T, bool CLIP, bool BLOCK>
+__global__ void __launch_bounds__(256) kb_spectral_dual(const SlotDesc *__restrict__ slots,
+                                                         const SlotStatus *__restrict__ status, WorkList wl) {
+  const int x = blockIdx.x % kXcds;
+  const int stride = gridDim.x / kXcds;
+  const int cnt = list_count(wl, x);
+  for (int j = blockIdx.x / kXcds; j < cnt; j += stride) {
+    const int it = list_item(wl, x, j);
+    const int s = it >> kItemSlotShift, local = it & kItemLocalMask;
+    if (status[s].state != kSlotRunning) continue;
+    const SlotDesc &sl = slots[s];
+    spectral_dual_ray<T, CLIP, BLOCK>(sl.sd, sl.p, sl.c, sl.y, sl.qS, sl.lambda,
+                                      local * (int)blockDim.x + (int)threadIdx.x);
+  }
+}
+
+template <bool BLOCK, bool WIDE>
+__global__ void __launch_bounds__(256) kb_back_primal(const SlotDesc *__restrict__ slots,
+                                                       const SlotStatus *__restrict__ status, WorkList wl,
+                                                       double2 *__restrict__ partial) {
+  __shared__ BpShared sh;
+  const int x = blockIdx.x % kXcds;
+  const int stride = gridDim.x / kXcds;
+  const int cnt = list_count(wl, x);
+  for (int j = blockIdx.x / kXcds; j < cnt; j += stride) {
+    const int it = list_item(wl, x, j);
+    const int s = it >> kItemSlotShift, local = it & kItemLocalMask;
+    if (status[s].state != kSlotRunning) continue;  // uniform over the workgroup
+    const SlotDesc &sl = slots[s];
+    const int ntx = (sl.sd.n + kBpTile - 1) / kBpTile;
+    const int ty = local / ntx, tx = local - ty * ntx;
+    const PrimalEpilogue epi{sl.pk_xy, sl.pk_yx, partial + sl.first_tile + local};
+    back_primal_tile<BLOCK, WIDE, true>(sl.sd, sl.qS, sl.f, sl.fbar, sl.lambda, tx, ty, sh, epi);
+  }
+}
+
+// One wave per slot: the tile partial sums in a fixed order, then the
+// stopping rule.
+__global__ void __launch_bounds__(64) kb_tick(const SlotDesc *__restrict__ slots, SlotStatus *__restrict__ status,
+                                               const double2 *__restrict__ partial) {
+  const int s = blockIdx.x;
+  if (status[s].state != kSlotRunning) return;
+  const int first = slots[s].first_tile, nt = slots[s].n_tiles;
+  double d2 = 0.0, n2 = 0.0;
+  for (int j = threadIdx.x; j < nt; j += 64) {
+    const double2 v = partial[first + j];
+    d2 += v.x;
+    n2 += v.y;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    d2 += __shfl_xor(d2, o, 64);
+    n2 += __shfl_xor(n2, o, 64);
+  }
+  if (threadIdx.x == 0) {
+    SlotStatus st = status[s];
+    st.iters += 1;
+    st.rel_change = n2 > 0.0 ? sqrt(d2 / n2) : (d2 > 0.0 ? INFINITY : 0.0);
+    if ((st.max_iter > 0 && st.iters >= st.max_iter) || (st.tol > 0.0f && st.rel_change <= (double)st.tol))
+      st.state = kSlotDone;
+    status[s] = st;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_batch_forward(const SlotDesc *slots, const SlotStatus *status, WorkList wl, int rays_per_wg,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(kb_forward, dim3((unsigned)wl.wgs), dim3((unsigned)rays_per_wg), 0, st, slots, status, wl);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_spectral_dual(const SlotDesc *slots, const SlotStatus *status, WorkList wl,
+                                      int rays_per_wg, bool clip, bool block, bool fp64, hipStream_t st) {
+  const dim3 g((unsigned)wl.wgs), b((unsigned)rays_per_wg);
+#define OSSCIR_BDUAL(T, C, B) hipLaunchKernelGGL((kb_spectral_dual<T, C, B>), g, b, 0, st, slots, status, wl)
+  if (fp64) {
+    if (clip) {
+      if (block) OSSCIR_BDUAL(double, true, true); else OSSCIR_BDUAL(double, true, false);
+    } else {
+      if (block) OSSCIR_BDUAL(double, false, true); else OSSCIR_BDUAL(double, false, false);
+    }
+  } else {
+    if (clip) {
+      if (block) OSSCIR_BDUAL(float, true, true); else OSSCIR_BDUAL(float, true, false);
+    } else {
+      if (block) OSSCIR_BDUAL(float, false, true); else OSSCIR_BDUAL(float, false, false);
+    }
+  }
+#undef OSSCIR_BDUAL
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_back_primal(const SlotDesc *slots, const SlotStatus *status, WorkList wl, bool block,
+                                    bool wide, double2 *partial, hipStream_t st) {
+  const dim3 g((unsigned)wl.wgs), b(kBpThreads);
+#define OSSCIR_BBP(B, W) hipLaunchKernelGGL((kb_back_primal<B, W>), g, b, 0, st, slots, status, wl, partial)
+  if (block) {
+    if (wide) OSSCIR_BBP(true, true); else OSSCIR_BBP(true, false);
+  } else {
+    if (wide) OSSCIR_BBP(false, true); else OSSCIR_BBP(false, false);
+  }
+#undef OSSCIR_BBP
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_tick(const SlotDesc *slots, SlotStatus *status, const double2 *partial, int n_slots,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(kb_tick, dim3((unsigned)n_slots), dim3(64), 0, st, slots, status, partial);
+  return hipGetLastError();
+}
+
+}  // namespace osscir

@@ -1,0 +1,46 @@
+// Host-side internals shared by the library's C-ABI translation units: the
+// plan object, the caller workspace layout and the error helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "device_math.h"
+#include "kernels.h"
+#include "osscir.h"
+
+struct osscir_plan_s {
+  int device = -1;
+  osscir::ScanDesc sd{};
+  osscir::RayLine *d_rays = nullptr;
+  osscir::ViewGeom *d_views = nullptr;
+  void *d_pack = nullptr;  // packed-image scratch of the standalone projector calls
+  float *d_rho = nullptr;
+  float *d_tab = nullptr;
+};
+
+namespace osscir {
+
+// Sets the thread's last-error message and returns code.
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+int check_plan(osscir_plan plan);
+
+#define OSSCIR_HIP(call, what)                                  \
+  do {                                                          \
+    hipError_t e_ = (call);                                     \
+    if (e_ != hipSuccess) return ::osscir::hip_fail(e_, what);  \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Caller workspace regions: p [3][L] f32 | qS [9][L] f32 | partial sums (f64)
+// | packed images of the forward projector.
+struct WorkLayout {
+  size_t p = 0, qS = 0, partial = 0, pack = 0, total = 0;
+};
+WorkLayout work_layout(const ScanDesc &sd);
+
+}  // namespace osscir

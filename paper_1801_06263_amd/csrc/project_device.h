@@ -50,8 +50,12 @@ struct ViewTile {
 };
 
 struct BpShared {
-  BinLDS bins[2][kBpMaxBins];
+  union {
+    BinLDS bins[2][kBpMaxBins];
+    float4 tile[kBpTile][kBpTile + 1];  // epilogues, after the last view
+  };
   ViewTile vt[kBpViewChunk];
+  double2 red[kBpThreads / 64];
 };
 
 __device__ __forceinline__ void tile_view_bounds(const ScanDesc &sd, const ViewGeom &vg, int tile_x, int tile_y,

@@ -1,5 +1,4 @@
-// Launchers of the projector kernels (projector.hip) and of the fused
-// back-projection epilogues (mocca.hip).
+// Launchers of the projector kernels (projector.hip).
 #pragma once
 
 #include "kernels.h"
@@ -12,6 +11,11 @@ size_t pack_scratch_bytes(const ScanDesc &sd);
 // p[c][l] = sum_k X_{l,k} f[c][k], c < nch (chunks of up to 3 channels);
 // pack: device scratch of pack_scratch_bytes().
 hipError_t launch_forward(const ScanDesc &sd, const float *f, int nch, float *p, void *pack, hipStream_t st);
+
+// Packs up to 3 channels of f into the two padded images of pack (the
+// layout launch_forward uses): row-contiguous copy first, then the
+// column-contiguous one.
+hipError_t launch_pack(const ScanDesc &sd, const float *f, int nch, void *pack, hipStream_t st);
 
 // b[c][k] = sum_l X_{l,k} q[c][l] (chunks of 9, 6, 3, 2 or 1 channels).
 hipError_t launch_back(const ScanDesc &sd, const float *q, int nch, float *b, hipStream_t st);

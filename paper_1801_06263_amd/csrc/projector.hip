@@ -10,232 +10,30 @@
 // so the two kernels accumulate exactly the same set of products.
 #include "device_math.h"
 #include "kernels.h"
+#include "forward_device.h"
 #include "project_device.h"
 #include "projector.h"
 
 namespace osscir {
 
-// ----------------------------------------------------------------- packing
-//
-// Up to three planar channels -> two interleaved float4 images with a zero
-// border of kPad pixels: pk_xy[iy + kPad][ix + kPad] (rows contiguous) and
-// pk_yx[ix + kPad][iy + kPad] (columns contiguous), written through a 32 x 32
-// LDS tile for the transposed copy.  The border lets the forward projector
-// read its candidate pixels without bounds checks: a candidate outside the
-// image reads 0 and adds w * 0 = 0.
+// ----------------------------------------------------------------- kernels
+
 __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ f, int n, int nch, float4 *__restrict__ pk_xy,
                                                float4 *__restrict__ pk_yx) {
   __shared__ float4 tile[32][33];
-  const int np = n + 2 * kPad;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;  // padded coordinates
-  const size_t nn = (size_t)n * n;
-  for (int r = ty; r < 32; r += 8) {
-    const int px = bx + tx, py = by + r;
-    const int ix = px - kPad, iy = py - kPad;
-    float4 val = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (ix >= 0 && ix < n && iy >= 0 && iy < n) {
-      const size_t k = (size_t)iy * n + ix;
-      val.x = f[k];
-      if (nch > 1) val.y = f[nn + k];
-      if (nch > 2) val.z = f[2 * nn + k];
-    }
-    if (px < np && py < np) pk_xy[(size_t)py * np + px] = val;
-    tile[r][tx] = val;
-  }
-  __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
-    const int py = by + tx, px = bx + r;
-    if (px < np && py < np) pk_yx[(size_t)px * np + py] = tile[tx][r];
-  }
-}
-
-// ----------------------------------------------------------------- forward
-//
-// One thread per ray, a workgroup = 256 consecutive detector bins of one view
-// (coalesced sinogram writes).  A ray walks its major axis (the image axis
-// closer to its direction); in each column (row) the line spans less than one
-// pixel of the minor axis, so the two pixels floor(y*) and floor(y*)+1 around
-// its crossing point y* hold every non-zero weight (within 0.11 degree of 45
-// degrees a third pixel is tested, against rounding).  Rays walking columns
-// read the column-contiguous packed image, rays walking rows the
-// row-contiguous one, so neighbouring lanes (neighbouring bins) read
-// neighbouring addresses; all lanes of a wave step through the same walk
-// index (the wave's union of walk ranges), several columns per step with
-// every load issued before the weights are formed.
-//
-// The FP64 offsets from the source are formed exactly as the back-projector
-// forms them: s - (double)i for integer i is exact, so the offset of the
-// second candidate, (s - iv0) - 1, equals s - (iv0 + 1) bit for bit.
-__device__ __forceinline__ int wave_min(int x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
-  return x;
-}
-__device__ __forceinline__ int wave_max(int x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
-  return x;
-}
-
-// Products are summed in FP32 over 16 columns at a time, then into an FP64
-// running sum (a ray crosses up to thousands of pixels).  kFpUnroll columns
-// are processed per step; the last step may run past the image by up to
-// kFpUnroll - 1 columns, which the zero border (kPad >= kFpUnroll) absorbs.
-constexpr int kFpUnroll = 4;
-static_assert(kPad >= kFpUnroll, "border must cover the unrolled tail");
-template <bool XMAJOR, bool THIRD, bool COUNT>
-__device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4 *__restrict__ img, double s_u,
-                                             double s_v, float slope, float base, const RayLine &ray, double &s0,
-                                             double &s1, double &s2) {
-  const int np = n + 2 * kPad;
-  constexpr int NC = THIRD ? 3 : 2;
-  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-  int pairs = 0;
-  for (int u = lo; u <= hi; u += kFpUnroll) {
-    float4 fv[kFpUnroll][NC];
-    float w[kFpUnroll][NC];
-    int iv0s[kFpUnroll], ives[kFpUnroll];
-#pragma unroll
-    for (int k = 0; k < kFpUnroll; ++k) {
-      const int uu = u + k;
-      const float ys = __fmaf_rn(slope, (float)uu, base);
-      const float fl = floorf(ys);
-      const int iv0 = min(max((int)fl, -2), n);
-      const int ive = (ys - fl < 0.5f) ? iv0 - 1 : iv0 + 2;
-      iv0s[k] = iv0;
-      ives[k] = ive;
-      if (!COUNT) {
-        const float4 *__restrict__ line = img + (size_t)(uu + kPad) * np + kPad;
-        fv[k][0] = line[iv0];
-        fv[k][1] = line[iv0 + 1];
-        if (THIRD) fv[k][2] = line[ive];
-      }
-      const double du = s_u - (double)uu;
-      const double dv0 = s_v - (double)iv0;
-      const double dv1 = dv0 - 1.0;
-      if (XMAJOR) {
-        w[k][0] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, du, dv0);
-        w[k][1] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, du, dv1);
-      } else {
-        w[k][0] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, dv0, du);
-        w[k][1] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, dv1, du);
-      }
-      if (THIRD) {
-        const double dve = s_v - (double)ive;
-        w[k][2] = XMAJOR ? chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, du, dve)
-                         : chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, dve, du);
-      }
-      // a column index past the image reads the zero border; its weight is irrelevant
-      if (uu >= n) {
-#pragma unroll
-        for (int j = 0; j < NC; ++j) w[k][j] = 0.0f;
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kFpUnroll; ++k)
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        if (COUNT) {
-          const int ivj = j == 0 ? iv0s[k] : (j == 1 ? iv0s[k] + 1 : ives[k]);
-          a0 += (w[k][j] > 0.0f && ivj >= 0 && ivj < n) ? 1.0f : 0.0f;
-        } else {
-          a0 = __fmaf_rn(w[k][j], fv[k][j].x, a0);
-          a1 = __fmaf_rn(w[k][j], fv[k][j].y, a1);
-          a2 = __fmaf_rn(w[k][j], fv[k][j].z, a2);
-        }
-      }
-    if (++pairs == 16 / kFpUnroll) {
-      s0 += (double)a0;
-      s1 += (double)a1;
-      s2 += (double)a2;
-      a0 = a1 = a2 = 0.0f;
-      pairs = 0;
-    }
-  }
-  s0 += (double)a0;
-  s1 += (double)a1;
-  s2 += (double)a2;
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2).  The flat workgroup index is remapped so that XCD x processes a
-// contiguous range of (view, bin-chunk) items: an arc of views whose rays
-// mostly share one major axis, and hence one of the two packed copies.
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ bool xcd_item(int nitems, int &item) {
-  const int b = blockIdx.x;
-  const int per = (nitems + kXcds - 1) / kXcds;
-  item = (b % kXcds) * per + b / kXcds;
-  return item < nitems;
+  pack_block(f, n, nch, pk_xy, pk_yx, blockIdx.x * 32, blockIdx.y * 32, tile);  // padded coordinates
 }
 
 template <bool COUNT>
 __global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__restrict__ pk_xy,
                                                   const float4 *__restrict__ pk_yx, float *__restrict__ p,
                                                   int p_stride, int nch) {
-  const int nchunk = (sd.n_bins + 255) / 256;
+  const int bs = blockDim.x;
+  const int nchunk = (sd.n_bins + bs - 1) / bs;
   int item;
   if (!xcd_item(sd.n_views * nchunk, item)) return;
   const int v = item / nchunk;
-  const int d = (item - v * nchunk) * 256 + threadIdx.x;
-  const int n = sd.n;
-  const bool active = d < sd.n_bins;
-  const ViewGeom vg = sd.views[v];
-  RayLine ray{1.0, 0.0, 0.0f, 0.0f, 0.0f, 0.0f};
-  bool xmajor = true, near45 = false;
-  float slope = 0.0f, base = 0.0f;
-  int iu_lo = n, iu_hi = -1;
-  if (active) {
-    ray = sd.rays[v * sd.n_bins + d];
-    // the line in index coordinates: nx ix + ny iy = nx sx + ny sy
-    const double sidx = ray.nx * vg.sx + ray.ny * vg.sy;
-    xmajor = fabs(ray.ny) >= fabs(ray.nx);
-    const double nu = xmajor ? ray.nx : ray.ny;  // along the walked axis
-    const double nv = xmajor ? ray.ny : ray.nx;  // along the minor axis, |nv| >= 1/sqrt 2
-    near45 = (fabs(nv) - fabs(nu)) < 2e-3;
-    slope = (float)(-nu / nv);
-    base = (float)(sidx / nv);
-    // walked indices where the crossing lies in (-1.5, n + 0.5), widened by one
-    iu_lo = 0;
-    iu_hi = n - 1;
-    if (fabsf(slope) > 1e-12f) {
-      const float t0 = (-1.5f - base) / slope;
-      const float t1 = ((float)n + 0.5f - base) / slope;
-      const float lo = fminf(t0, t1), hi = fmaxf(t0, t1);
-      iu_lo = max(iu_lo, (int)floorf(fmaxf(lo, -4.0f)) - 1);
-      iu_hi = min(iu_hi, (int)ceilf(fminf(hi, (float)n + 4.0f)) + 1);
-    } else if (!(base > -1.5f && base < (float)n + 0.5f)) {
-      iu_lo = n;
-      iu_hi = -1;
-    }
-  }
-  const int lo = wave_min(iu_lo), hi = wave_max(iu_hi);
-  const bool any45 = __any(near45);
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  if (active) {
-    if (xmajor) {
-      if (any45)
-        forward_walk<true, true, COUNT>(lo, hi, n, pk_yx, vg.sx, vg.sy, slope, base, ray, a0, a1, a2);
-      else
-        forward_walk<true, false, COUNT>(lo, hi, n, pk_yx, vg.sx, vg.sy, slope, base, ray, a0, a1, a2);
-    } else {
-      if (any45)
-        forward_walk<false, true, COUNT>(lo, hi, n, pk_xy, vg.sy, vg.sx, slope, base, ray, a0, a1, a2);
-      else
-        forward_walk<false, false, COUNT>(lo, hi, n, pk_xy, vg.sy, vg.sx, slope, base, ray, a0, a1, a2);
-    }
-  }
-  if (!active) return;
-  const int l = v * sd.n_bins + d;
-  if (COUNT) {
-    reinterpret_cast<int *>(p)[l] = (int)a0;
-    return;
-  }
-  p[l] = (float)a0;
-  if (nch > 1) p[p_stride + l] = (float)a1;
-  if (nch > 2) p[2 * p_stride + l] = (float)a2;
+  forward_rays<COUNT>(sd, pk_xy, pk_yx, p, p_stride, nch, v, (item - v * nchunk) * bs);
 }
 
 // ----------------------------------------------------------------- back
@@ -283,6 +81,14 @@ hipError_t launch_forward(const ScanDesc &sd, const float *f, int nch, float *p,
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_pack(const ScanDesc &sd, const float *f, int nch, void *pack, hipStream_t st) {
+  const size_t np = (size_t)sd.n + 2 * kPad;
+  float4 *pk_xy = reinterpret_cast<float4 *>(pack);
+  const dim3 pgrid((unsigned)((np + 31) / 32), (unsigned)((np + 31) / 32));
+  hipLaunchKernelGGL(k_pack, pgrid, dim3(256), 0, st, f, sd.n, nch, pk_xy, pk_xy + np * np);
+  return hipGetLastError();
 }
 
 hipError_t launch_count(const ScanDesc &sd, int *nnz, hipStream_t st) {

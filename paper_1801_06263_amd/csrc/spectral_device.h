@@ -1,0 +1,332 @@
+// Per-ray spectral model and dual step, and the per-tile back-projection
+// fused with the primal step (Sec. II and III of arXiv 1801.06263), shared by
+// the single-scan kernels (spectral.hip) and the batched kernels
+// (batch.hip).
+//
+// One thread per ray.  The energy loop reads the spectral table at a uniform
+// address (scalar loads, SGPR operands) and accumulates, per window, the
+// model sum g_w, the Jacobian rows a_w = sum_i s_{w,i} softexp'(-z_i) mu_i and,
+// for the clipped curvature, Hb_w = sum_i s_{w,i} softexp''(-z_i) mu_i mu_i^T.
+// The per-ray tail (3x3 eigen-clip, 4x4 dual solve) runs in FP32 or FP64.
+#pragma once
+
+#include "device_math.h"
+#include "kernels.h"
+#include "project_device.h"
+
+namespace osscir {
+
+// upper-triangle index of (m, n), m <= n, in a symmetric 3x3
+__device__ __forceinline__ constexpr int ut(int m, int n) { return m == 0 ? n : (m == 1 ? 2 + n : 5); }
+
+// SHIFT: the sums are taken with exp(-(z - zshift)) in place of exp(-z), for
+// a ray whose every z_i >= zshift > 0 (all energies on the exponential
+// branch).  The ratios a_w / g_w and Hb_w / g_w are unchanged; g_w carries
+// the factor exp(zshift).
+template <bool NEED_A, bool NEED_HB, bool SHIFT = false>
+__device__ __forceinline__ void energy_sums(const ScanDesc &sd, float p0, float p1, float p2, float g[kWin],
+                                            float a[kWin * kMat], float hb[kWin * 6], float zshift = 0.0f) {
+#pragma unroll
+  for (int w = 0; w < kWin; ++w) g[w] = 0.0f;
+  if (NEED_A) {
+#pragma unroll
+    for (int j = 0; j < kWin * kMat; ++j) a[j] = 0.0f;
+  }
+  if (NEED_HB) {
+#pragma unroll
+    for (int j = 0; j < kWin * 6; ++j) hb[j] = 0.0f;
+  }
+  const float *__restrict__ tab = sd.tab;
+  for (int i = 0; i < sd.n_energy; ++i) {
+    const float *t = tab + i * kTab;
+    float E, E1, E2;
+    if (SHIFT) {
+      const float zs = __fmaf_rn(t[kTabMu + 2], p2, __fmaf_rn(t[kTabMu + 1], p1, __fmaf_rn(t[kTabMu], p0, -zshift)));
+      E = E1 = E2 = __expf(-zs);
+    } else {
+      const float z = __fmaf_rn(t[kTabMu + 2], p2, __fmaf_rn(t[kTabMu + 1], p1, t[kTabMu] * p0));
+      softexp3(z, E, E1, E2);
+    }
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) g[w] = __fmaf_rn(t[kTabS + w], E, g[w]);
+    if (NEED_A) {
+#pragma unroll
+      for (int j = 0; j < kWin * kMat; ++j) a[j] = __fmaf_rn(t[kTabSMu + j], E1, a[j]);
+    }
+    if (NEED_HB) {
+#pragma unroll
+      for (int j = 0; j < kWin * 6; ++j) hb[j] = __fmaf_rn(t[kTabSMuMu + j], E2, hb[j]);
+    }
+  }
+}
+
+// Model sums of one ray with a rescue for transmissions below FP32 range:
+// if a window sum underflows (an iterate far outside the physical range),
+// the sums are recomputed with the exponent shifted by min_i z_i.  Returns
+// the factor (<= 1) that turns the returned g_w into the true sums.
+template <bool NEED_A, bool NEED_HB>
+__device__ __forceinline__ float energy_sums_safe(const ScanDesc &sd, float p0, float p1, float p2, float g[kWin],
+                                                  float a[kWin * kMat], float hb[kWin * 6]) {
+  energy_sums<NEED_A, NEED_HB>(sd, p0, p1, p2, g, a, hb);
+  const float gmin = fminf(fminf(g[0], g[1]), fminf(g[2], g[3]));
+  if (gmin >= 1e-30f) return 1.0f;
+  float zmin = 3.0e38f;
+  for (int i = 0; i < sd.n_energy; ++i) {
+    const float *t = sd.tab + i * kTab;
+    zmin = fminf(zmin, __fmaf_rn(t[kTabMu + 2], p2, __fmaf_rn(t[kTabMu + 1], p1, t[kTabMu] * p0)));
+  }
+  if (!(zmin > 0.0f)) return 1.0f;  // some energy on the linear branch: no underflow possible
+  energy_sums<NEED_A, NEED_HB, true>(sd, p0, p1, p2, g, a, hb, zmin);
+  return __expf(-zmin);
+}
+
+// Per-ray p-space Hessian  H = sum_w c_w a_w a_w^T - sum_w (r_w / g_w) Hb_w
+// (the ray-l block of -Z^T diag(B^T r) Z + Z^T A^T diag(chat + r) A Z, using
+// chat + r = c), with a_w already divided by g_w.
+template <typename T>
+__device__ __forceinline__ void ray_hessian(const T a[kWin][kMat], const T cw[kWin], const T rg[kWin],
+                                            const float hb[kWin * 6], T H[6]) {
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int n = m; n < 3; ++n) {
+      T h = T(0);
+#pragma unroll
+      for (int w = 0; w < kWin; ++w) h += cw[w] * a[w][m] * a[w][n] - rg[w] * (T)hb[w * 6 + ut(m, n)];
+      H[ut(m, n)] = h;
+    }
+}
+
+// ---------------------------------------------------------------- dual step
+//
+// y <- y + Sigma (Sigma + D)^-1 (r - y),  q = G^T y,  and the per-ray
+// preconditioner terms S (block) or h (diag) for the back-projection.
+// CLIP: D = G^+T H^+ G^+ built from the column-equilibrated G and solved as
+// (I + Sigma^-1/2 D Sigma^-1/2) z = Sigma^-1/2 (r - y).
+template <typename T, bool CLIP, bool BLOCK>
+__device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const float *__restrict__ p,
+                                                  const float *__restrict__ c, float *__restrict__ y,
+                                                  float *__restrict__ qS, float lambda, int l) {
+  const int L = sd.n_rays;
+  if (l >= L) return;
+  const float rho = sd.rho[l];
+  if (!(rho > 0.0f)) {
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) y[w * L + l] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) qS[j * L + l] = 0.0f;
+    return;
+  }
+  float g[kWin], af[kWin * kMat], hb[kWin * 6];
+  const float scale = energy_sums_safe<true, CLIP>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb);
+
+  T a[kWin][kMat], cw[kWin], rw[kWin], yw[kWin], sig[kWin];
+#pragma unroll
+  for (int w = 0; w < kWin; ++w) {
+    const float cf = c[w * L + l];
+    cw[w] = (T)cf;
+    rw[w] = (T)(cf - sd.n0[w] * g[w] * scale);
+    yw[w] = (T)y[w * L + l];
+    const T ig = T(1) / (T)g[w];
+#pragma unroll
+    for (int m = 0; m < kMat; ++m) a[w][m] = (T)af[w * kMat + m] * ig;
+  }
+  // step lengths and the per-ray preconditioner terms
+  T extra[6];
+  const T lr = (T)lambda * (T)rho;
+  if (BLOCK) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) extra[j] = T(0);
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) {
+      const T nrm = sqrt(a[w][0] * a[w][0] + a[w][1] * a[w][1] + a[w][2] * a[w][2]);
+      sig[w] = T(1) / (lr * nrm);
+      const T inv = T(1) / nrm;
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int n = m; n < 3; ++n) extra[ut(m, n)] += a[w][m] * a[w][n] * inv;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) extra[m] = T(0);
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) {
+      const T l1 = fabs(a[w][0]) + fabs(a[w][1]) + fabs(a[w][2]);
+      sig[w] = T(1) / (lr * l1);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) extra[m] += fabs(a[w][m]);
+    }
+  }
+  // dual step
+  if (!CLIP) {
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) yw[w] = (cw[w] * yw[w] + sig[w] * rw[w]) / (cw[w] + sig[w]);
+  } else {
+    T rg[kWin];
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) rg[w] = rw[w] / (T)g[w];
+    T h[6], hp[6];
+    ray_hessian<T>(a, cw, rg, hb, h);
+    clip_negative_curvature<T, sizeof(T) == 8 ? 8 : 6>(h, hp);
+    // column equilibration of G
+    T cn[3], gt[kWin][kMat];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      cn[m] = sqrt(a[0][m] * a[0][m] + a[1][m] * a[1][m] + a[2][m] * a[2][m] + a[3][m] * a[3][m]);
+      const T ic = T(1) / cn[m];
+#pragma unroll
+      for (int w = 0; w < kWin; ++w) gt[w][m] = a[w][m] * ic;
+    }
+    T gram[6];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int n = m; n < 3; ++n) {
+        T s = T(0);
+#pragma unroll
+        for (int w = 0; w < kWin; ++w) s += gt[w][m] * gt[w][n];
+        gram[ut(m, n)] = s;
+      }
+    T gi[3][3];
+    spd3_inverse<T>(gram, gi);
+    // P~ = Sigma^-1/2 G~ Gram^-1   (rows w)
+    T ss[kWin], P[kWin][3];
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) {
+      ss[w] = sqrt(sig[w]);
+      const T is = T(1) / ss[w];
+#pragma unroll
+      for (int n = 0; n < 3; ++n) P[w][n] = (gt[w][0] * gi[0][n] + gt[w][1] * gi[1][n] + gt[w][2] * gi[2][n]) * is;
+    }
+    // H^ = C^-1 H^+ C^-1
+    T Hh[3][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int n = 0; n < 3; ++n) Hh[m][n] = hp[m <= n ? ut(m, n) : ut(n, m)] / (cn[m] * cn[n]);
+    // M = P~ H^ P~^T
+    T PH[kWin][3], Mm[kWin][kWin];
+#pragma unroll
+    for (int w = 0; w < kWin; ++w)
+#pragma unroll
+      for (int n = 0; n < 3; ++n) PH[w][n] = P[w][0] * Hh[0][n] + P[w][1] * Hh[1][n] + P[w][2] * Hh[2][n];
+#pragma unroll
+    for (int w = 0; w < kWin; ++w)
+#pragma unroll
+      for (int v = 0; v < kWin; ++v) Mm[w][v] = PH[w][0] * P[v][0] + PH[w][1] * P[v][1] + PH[w][2] * P[v][2];
+    T bt[kWin], z[kWin];
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) bt[w] = (rw[w] - yw[w]) / ss[w];
+    unit_plus_psd4_solve<T>(Mm, bt, z);
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) yw[w] = yw[w] + ss[w] * z[w];
+  }
+  // outputs: y, q = G^T y, and S (block) or h (diag)
+#pragma unroll
+  for (int w = 0; w < kWin; ++w) y[w * L + l] = (float)yw[w];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const T qm = a[0][m] * yw[0] + a[1][m] * yw[1] + a[2][m] * yw[2] + a[3][m] * yw[3];
+    qS[m * L + l] = (float)qm;
+  }
+  if (BLOCK) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) qS[(3 + j) * L + l] = (float)extra[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) qS[(3 + j) * L + l] = (float)extra[j];
+  }
+}
+
+// ---------------------------------------------------------------- primal
+//
+// Back-projection of [q; S] (or [q; h]) fused with the primal step and the
+// extrapolation:  block  f' = f - lambda (sum_l X S_l)^-1 (sum_l X q_l)
+//                 diag   f'_m = f_m - lambda (sum_l X q_l)_m / (sum_l X h_l)_m
+//                 fbar'  = 2 f' - f.
+// The 3x3 solve takes the FP64 sums directly (equilibrated Cholesky).
+//
+// EPI (batched iteration) adds two outputs: fbar' written into the packed
+// images the next forward projection reads (interior only; the zero border
+// is written once when the scan is bound), the column-contiguous copy
+// transposed through LDS; and the tile's FP64 sums of |f' - f|^2 and |f'|^2
+// (fixed-order reduction) for the relative-change stopping rule.
+struct PrimalEpilogue {
+  float4 *pk_xy, *pk_yx;
+  double2 *partial;  // this tile's (sum |f' - f|^2, sum |f'|^2)
+};
+
+template <bool BLOCK, bool WIDE, bool EPI>
+__device__ __forceinline__ void back_primal_tile(const ScanDesc &sd, const float *__restrict__ qS,
+                                                 float *__restrict__ f, float *__restrict__ fbar, float lambda,
+                                                 int tile_x, int tile_y, BpShared &sh, const PrimalEpilogue &epi) {
+  constexpr int NCH = BLOCK ? 9 : 6;
+  double acc[NCH];
+  back_accumulate<NCH, WIDE>(sd, tile_x, tile_y, qS, sd.n_rays, acc, sh);
+  const int tx = threadIdx.x & (kBpTile - 1), ty = threadIdx.x / kBpTile;
+  const int ix = tile_x * kBpTile + tx;
+  const int iy = tile_y * kBpTile + ty;
+  const bool inside = ix < sd.n && iy < sd.n;
+  if (!EPI && !inside) return;
+  const int nn = sd.n * sd.n;
+  const int k = iy * sd.n + ix;
+  float fo[3] = {0.0f, 0.0f, 0.0f}, fn[3] = {0.0f, 0.0f, 0.0f}, fb[3] = {0.0f, 0.0f, 0.0f};
+  if (inside) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) fo[m] = f[m * nn + k];
+    const double lam = (double)lambda;
+    if (BLOCK) {
+      double x[3] = {0.0, 0.0, 0.0};
+      if (acc[3] > 0.0 && acc[6] > 0.0 && acc[8] > 0.0) spd3_solve<double>(acc + 3, acc, x);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) fn[m] = (float)((double)fo[m] - lam * x[m]);
+    } else {
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+        fn[m] = acc[3 + m] > 0.0 ? (float)((double)fo[m] - lam * acc[m] / acc[3 + m]) : fo[m];
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      fb[m] = 2.0f * fn[m] - fo[m];
+      f[m * nn + k] = fn[m];
+      fbar[m * nn + k] = fb[m];
+    }
+  }
+  if (!EPI) return;
+  // packed copies of fbar' and the tile's change sums
+  const int np = sd.n + 2 * kPad;
+  const float4 v4 = make_float4(fb[0], fb[1], fb[2], 0.0f);
+  if (inside) epi.pk_xy[(size_t)(iy + kPad) * np + (ix + kPad)] = v4;
+  double d2 = 0.0, n2 = 0.0;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const double dm = (double)fn[m] - (double)fo[m];
+    d2 += dm * dm;
+    n2 += (double)fn[m] * (double)fn[m];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    d2 += __shfl_xor(d2, o, 64);
+    n2 += __shfl_xor(n2, o, 64);
+  }
+  sh.tile[ty][tx] = v4;  // the last view's barrier has released the staging buffer
+  if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = make_double2(d2, n2);
+  __syncthreads();
+  {
+    const int cx = threadIdx.x / kBpTile, ry = threadIdx.x & (kBpTile - 1);  // column cx, row ry of the tile
+    const int jx = tile_x * kBpTile + cx, jy = tile_y * kBpTile + ry;
+    if (jx < sd.n && jy < sd.n) epi.pk_yx[(size_t)(jx + kPad) * np + (jy + kPad)] = sh.tile[ry][cx];
+  }
+  if (threadIdx.x == 0) {
+    double2 s = sh.red[0];
+#pragma unroll
+    for (int w = 1; w < kBpThreads / 64; ++w) {
+      s.x += sh.red[w].x;
+      s.y += sh.red[w].y;
+    }
+    *epi.partial = s;
+  }
+}
+
+}  // namespace osscir

@@ -44,6 +44,18 @@ class _State(ctypes.Structure):
                 ("work", c_void_p), ("work_bytes", c_size_t)]
 
 
+class _SlotStatus(ctypes.Structure):
+    _fields_ = [("state", c_int32), ("iters", c_int32), ("rel_change", c_double)]
+
+
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [("fp_rays", c_int32), ("fp_wgs", c_int32), ("fp_xcd", c_int32),
+                ("spec_rays", c_int32), ("spec_wgs", c_int32), ("spec_xcd", c_int32),
+                ("bp_wgs", c_int32), ("bp_xcd", c_int32)]
+
+
+SLOT_EMPTY, SLOT_RUNNING, SLOT_DONE = 0, 1, 2
+
 # name -> (restype, argtypes) for every entry point of include/osscir.h
 SIGNATURES = {
     "osscir_plan_create": (c_int32, [ctypes.POINTER(_Geometry), ctypes.POINTER(_Spectral), ctypes.POINTER(c_void_p)]),
@@ -63,6 +75,16 @@ SIGNATURES = {
     "osscir_mocca_stage": (c_int32, [c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_State), c_int32, c_void_p]),
     "osscir_ray_nnz": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "osscir_dtpl": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "osscir_batch_create": (c_int32, [ctypes.POINTER(_Params), c_int32, ctypes.POINTER(c_void_p)]),
+    "osscir_batch_destroy": (c_int32, [c_void_p]),
+    "osscir_batch_set_slot": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.POINTER(_State), c_double, c_int32,
+                                        c_double, c_void_p]),
+    "osscir_batch_clear_slot": (c_int32, [c_void_p, c_int32]),
+    "osscir_batch_iterate": (c_int32, [c_void_p, c_int32, c_int32, c_void_p]),
+    "osscir_batch_status": (c_int32, [c_void_p, ctypes.POINTER(_SlotStatus), c_void_p]),
+    "osscir_batch_get_config": (c_int32, [c_void_p, ctypes.POINTER(_BatchConfig)]),
+    "osscir_batch_set_config": (c_int32, [c_void_p, ctypes.POINTER(_BatchConfig)]),
+    "osscir_batch_tune": (c_int32, [c_void_p, c_int32, ctypes.POINTER(_BatchConfig), c_void_p]),
     "osscir_last_error": (ctypes.c_char_p, []),
     "osscir_version": (ctypes.c_char_p, []),
 }
@@ -283,6 +305,75 @@ class Plan:
                                 _dev(c, (4, *self.sino_shape), torch.float32, "c"), _dev(out), _dev(work),
                                 work.numel(), _stream_handle(stream)))
         return out
+
+
+BATCH_CONFIG_FIELDS = [name for name, _ in _BatchConfig._fields_]
+
+
+class Batch:
+    """Many scans advanced together, one launch per stage for the whole batch.
+
+    Slots hold (plan, state, lambda, max_iter, tol); modes (precond,
+    curvature, fp64_small) are shared.  The binding keeps the bound plans and
+    states alive while they are bound.
+    """
+
+    def __init__(self, modes: Params, max_slots: int):
+        lib = load_library()
+        h = c_void_p()
+        prm = modes.to_c()
+        _check(lib.osscir_batch_create(ctypes.byref(prm), int(max_slots), ctypes.byref(h)))
+        self._h = h
+        self.max_slots = int(max_slots)
+        self._bound = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(_lib.osscir_batch_destroy(self._h))
+            self._h = None
+            self._bound = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_slot(self, slot: int, plan: Plan, state: State, lam: float, max_iter: int = 0, tol: float = 0.0,
+                 stream=None):
+        st = plan._c_state(state)
+        _check(_lib.osscir_batch_set_slot(self._h, int(slot), plan._h, ctypes.byref(st), float(lam), int(max_iter),
+                                          float(tol), _stream_handle(stream)))
+        self._bound[int(slot)] = (plan, state)
+
+    def clear_slot(self, slot: int):
+        _check(_lib.osscir_batch_clear_slot(self._h, int(slot)))
+        self._bound.pop(int(slot), None)
+
+    def iterate(self, n_iter: int, use_graph: bool = True, stream=None):
+        _check(_lib.osscir_batch_iterate(self._h, int(n_iter), int(bool(use_graph)), _stream_handle(stream)))
+
+    def status(self, stream=None):
+        """List of (state, iters, rel_change) per slot (synchronises the stream)."""
+        arr = (_SlotStatus * self.max_slots)()
+        _check(_lib.osscir_batch_status(self._h, arr, _stream_handle(stream)))
+        return [(a.state, a.iters, a.rel_change) for a in arr]
+
+    def get_config(self) -> dict:
+        c = _BatchConfig()
+        _check(_lib.osscir_batch_get_config(self._h, ctypes.byref(c)))
+        return {k: int(getattr(c, k)) for k in BATCH_CONFIG_FIELDS}
+
+    def set_config(self, **kw):
+        cfg = self.get_config()
+        cfg.update(kw)
+        c = _BatchConfig(*[int(cfg[k]) for k in BATCH_CONFIG_FIELDS])
+        _check(_lib.osscir_batch_set_config(self._h, ctypes.byref(c)))
+
+    def tune(self, iters_per_trial: int = 2, stream=None) -> dict:
+        c = _BatchConfig()
+        _check(_lib.osscir_batch_tune(self._h, int(iters_per_trial), ctypes.byref(c), _stream_handle(stream)))
+        return {k: int(getattr(c, k)) for k in BATCH_CONFIG_FIELDS}
 
 
 def version() -> str:
