@@ -64,6 +64,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", default="24,72", help="view-subset sizes of the oracle sample")
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--legs", default="single,batched",
+                    help="comma list of single (the 512^2 iteration rate), batched; a run without "
+                         "'single' prints only the other legs (for profiling)")
+    ap.add_argument("--batch-iters", type=int, default=100,
+                    help="iterations per slice of the batched leg (0 skips it)")
+    ap.add_argument("--batch-per-size", type=int, default=6, help="slices per size in the batched mix")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) to calibrate HBM byte counters")
     return ap.parse_args()
@@ -141,6 +147,92 @@ def cpu_baseline(pr, lam, precond, curvature, view_counts):
     return {"value": 1.0 / t_full, "unit": "iter/s", "cores": 1, "kind": "oracle", "sample": sample}
 
 
+def library_counts(plan, pr):
+    """Poisson counts at the phantom from the library's own counts model."""
+    import numpy as np
+    import torch
+
+    import synth
+    g = pr.geom
+    p = plan.forward_project(torch.as_tensor(pr.f_true.astype(np.float32)).cuda())
+    chat = plan.spectral_model(p, torch.zeros(4, g.n_views, g.n_bins, device="cuda"))["chat"]
+    c = synth.poisson_counts(chat.double().cpu().numpy(), pr.seed).astype(np.float32)
+    return torch.from_numpy(c).cuda()
+
+
+BATCH_LAM = 2e-8
+
+
+def batched_leg(n_iter: int, per_size: int):
+    """Batched solves/s: the mixed-size slices (128^2 .. 512^2, views 1.4 n,
+    bins 2 n) each solved for n_iter iterations, as one batch (one launch
+    per stage for all slices, graph replay, tuned launch shapes) and as the
+    plain loop that runs each scan alone with osscir_mocca_iterate, one after
+    the other, on the same stream.  Both give bit-identical maps."""
+    import torch
+
+    import synth
+    from paper_1801_06263_amd import Batch, Params, Plan
+
+    mix = synth.batch_mix(per_size)
+    plans, counts = {}, []
+    for pr in mix:
+        n = pr.geom.n
+        if n not in plans:
+            plans[n] = Plan(pr.geom, pr.spec)
+        counts.append(library_counts(plans[n], pr))
+    params = Params(BATCH_LAM, "block", "clip", True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    # the plain per-scan loop
+    seq = [plans[pr.geom.n].new_state(c) for pr, c in zip(mix, counts)]
+    warm = plans[mix[0].geom.n].new_state(counts[0])
+    plans[mix[0].geom.n].mocca_iterate(warm, params, 2)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for pr, st in zip(mix, seq):
+        plans[pr.geom.n].mocca_iterate(st, params, n_iter)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_seq = ev[0].elapsed_time(ev[1]) * 1e-3
+    # the batch: tune, capture the graph on a throw-away iteration, rebind fresh states
+    b = Batch(params, len(mix))
+    tmp = [plans[pr.geom.n].new_state(c) for pr, c in zip(mix, counts)]
+    for i, (pr, st) in enumerate(zip(mix, tmp)):
+        b.set_slot(i, plans[pr.geom.n], st, BATCH_LAM)
+    t_tune = time.perf_counter()
+    cfg = b.tune(2)
+    t_tune = time.perf_counter() - t_tune
+    b.iterate(1, use_graph=True)
+    del tmp
+    states = [plans[pr.geom.n].new_state(c) for pr, c in zip(mix, counts)]
+    for i, (pr, st) in enumerate(zip(mix, states)):
+        b.set_slot(i, plans[pr.geom.n], st, BATCH_LAM, max_iter=n_iter)
+    b.iterate(0)  # uploads the new slot table outside the timed region
+    torch.cuda.synchronize()
+    ev[2].record()
+    b.iterate(n_iter, use_graph=True)
+    ev[3].record()
+    torch.cuda.synchronize()
+    t_batch = ev[2].elapsed_time(ev[3]) * 1e-3
+    status = b.status()
+    done = all(status[i][0] == 2 and status[i][1] == n_iter for i in range(len(mix)))
+    equal = all(torch.equal(a.f, z.f) and torch.equal(a.y, z.y) for a, z in zip(states, seq))
+    finite = all(bool(torch.isfinite(st.f).all().item()) for st in states)
+    sizes = sorted(plans)
+    return {
+        "solves_per_s": round(len(mix) / t_batch, 3),
+        "sequential_solves_per_s": round(len(mix) / t_seq, 3),
+        "speedup_vs_sequential": round(t_seq / t_batch, 3),
+        "ms_per_batched_iteration": round(t_batch * 1e3 / n_iter, 3),
+        "ms_per_sequential_sweep": round(t_seq * 1e3 / n_iter, 3),
+        "iterations_per_solve": n_iter,
+        "slices": f"{len(mix)}: {per_size} each of " + "/".join(f"{n}^2" for n in sizes)
+                  + " (views 1.4 n, bins 2 n, 120 energies, I0 1e6)",
+        "lambda": BATCH_LAM, "graph": True, "tuned_config": cfg, "tune_s": round(t_tune, 2),
+        "all_done_at_budget": done, "bitwise_equal_to_sequential": equal, "state_finite": finite,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -157,6 +249,13 @@ def main():
     from paper_1801_06263_amd import Params, Plan
 
     torch.cuda.set_device(0)
+    legs = set(args.legs.split(","))
+    if "single" not in legs:
+        line = {}
+        if "batched" in legs:
+            line["batched"] = batched_leg(args.batch_iters, args.batch_per_size)
+        print(json.dumps(line), flush=True)
+        return
     pr = synth.problem(args.workload)
     geom = pr.geom
     lam = args.lam if args.lam is not None else DEFAULT_LAM[args.workload]
@@ -267,6 +366,11 @@ def main():
                 "frac": round(hbm_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 5)},
         "state_finite": finite,
     }
+    if "batched" in legs and args.batch_iters > 0:
+        print(f"[bench] batched leg: {args.batch_per_size} slices per size, {args.batch_iters} iterations each",
+              file=sys.stderr, flush=True)
+        line["batched"] = batched_leg(args.batch_iters, args.batch_per_size)
+        print(f"[bench] batched: {line['batched']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         views = [int(v) for v in args.cpu_views.split(",")]
         print(f"[bench] cpu baseline: oracle on {views}-view subsets", file=sys.stderr, flush=True)

@@ -17,12 +17,37 @@
 
 namespace osscir {
 
-__device__ __forceinline__ int list_count(const WorkList &wl, int x) { return wl.buf[x]; }
+// Work lists, slot descriptors and status are read-only while a stage
+// kernel runs: read through the scalar cache.
+__device__ __forceinline__ int list_count(const WorkList &wl, int x) { return as_const(wl.buf)[x]; }
 __device__ __forceinline__ int list_item(const WorkList &wl, int x, int j) {
-  return wl.buf[kListHeader + x * wl.cap + j];
+  return as_const(wl.buf)[kListHeader + x * wl.cap + j];
+}
+// The slot's descriptor in SGPRs, its buffers marked as global memory (the
+// pointers are re-read as pointers: a pointer rebuilt from words would be
+// accessed with flat instructions).
+__device__ __forceinline__ SlotDesc load_slot(const SlotDesc *slots, int s) {
+  SlotDesc d = load_uniform(slots + s);
+  const OSSCIR_CONST SlotDesc *q = as_const(slots + s);
+  d.sd.rays = as_global(q->sd.rays);
+  d.sd.rho = as_global(q->sd.rho);
+  d.sd.views = as_global(q->sd.views);
+  d.f = as_global(q->f);
+  d.fbar = as_global(q->fbar);
+  d.y = as_global(q->y);
+  d.c = as_global(q->c);
+  d.p = as_global(q->p);
+  d.qS = as_global(q->qS);
+  d.pk_xy = as_global(q->pk_xy);
+  d.pk_yx = as_global(q->pk_yx);
+  return d;
 }
 
-__global__ void __launch_bounds__(256) kb_forward(const SlotDesc *__restrict__ slots,
+__device__ __forceinline__ bool slot_running(const SlotStatus *status, int s) {
+  return as_const(status)[s].state == kSlotRunning;
+}
+
+__global__ void __launch_bounds__(256, 6) kb_forward(const SlotDesc *__restrict__ slots,
                                                    const SlotStatus *__restrict__ status, WorkList wl) {
   const int x = blockIdx.x % kXcds;
   const int stride = gridDim.x / kXcds;
@@ -31,8 +56,8 @@ __global__ void __launch_bounds__(256) kb_forward(const SlotDesc *__restrict__ s
   for (int j = blockIdx.x / kXcds; j < cnt; j += stride) {
     const int it = list_item(wl, x, j);
     const int s = it >> kItemSlotShift, local = it & kItemLocalMask;
-    if (status[s].state != kSlotRunning) continue;
-    const SlotDesc &sl = slots[s];
+    if (!slot_running(status, s)) continue;
+    const SlotDesc sl = load_slot(slots, s);
     const int nchunk = (sl.sd.n_bins + R - 1) / R;
     const int v = local / nchunk;
     forward_rays<false>(sl.sd, sl.pk_xy, sl.pk_yx, sl.p, sl.sd.n_rays, 3, v, (local - v * nchunk) * R);
@@ -48,8 +73,8 @@ __global__ void __launch_bounds__(256) kb_spectral_dual(const SlotDesc *__restri
   for (int j = blockIdx.x / kXcds; j < cnt; j += stride) {
     const int it = list_item(wl, x, j);
     const int s = it >> kItemSlotShift, local = it & kItemLocalMask;
-    if (status[s].state != kSlotRunning) continue;
-    const SlotDesc &sl = slots[s];
+    if (!slot_running(status, s)) continue;
+    const SlotDesc sl = load_slot(slots, s);
     spectral_dual_ray<T, CLIP, BLOCK>(sl.sd, sl.p, sl.c, sl.y, sl.qS, sl.lambda,
                                       local * (int)blockDim.x + (int)threadIdx.x);
   }
@@ -66,8 +91,8 @@ __global__ void __launch_bounds__(256) kb_back_primal(const SlotDesc *__restrict
   for (int j = blockIdx.x / kXcds; j < cnt; j += stride) {
     const int it = list_item(wl, x, j);
     const int s = it >> kItemSlotShift, local = it & kItemLocalMask;
-    if (status[s].state != kSlotRunning) continue;  // uniform over the workgroup
-    const SlotDesc &sl = slots[s];
+    if (!slot_running(status, s)) continue;  // uniform over the workgroup
+    const SlotDesc sl = load_slot(slots, s);
     const int ntx = (sl.sd.n + kBpTile - 1) / kBpTile;
     const int ty = local / ntx, tx = local - ty * ntx;
     const PrimalEpilogue epi{sl.pk_xy, sl.pk_yx, partial + sl.first_tile + local};

@@ -171,7 +171,7 @@ __device__ __forceinline__ void forward_rays(const ScanDesc &sd, const float4 *_
   const int d = d0 + threadIdx.x;
   const int n = sd.n;
   const bool active = d < sd.n_bins;
-  const ViewGeom vg = sd.views[v];
+  const ViewGeom vg = load_uniform(sd.views + v);
   RayLine ray{1.0, 0.0, 0.0f, 0.0f, 0.0f, 0.0f};
   bool xmajor = true, near45 = false;
   float slope = 0.0f, base = 0.0f;

@@ -51,4 +51,36 @@ struct ScanDesc {
   const float *tab;     // [I][kTab]
 };
 
+// Pointers into the constant address space: loads through them at a
+// uniform address become scalar-cache loads into SGPRs, also after stores
+// of the same kernel (the memory is read-only for the kernel's lifetime:
+// tables, descriptors, work lists).
+#define OSSCIR_CONST __attribute__((address_space(4)))
+
+template <typename T>
+__device__ __forceinline__ const OSSCIR_CONST T *as_const(const T *p) {
+  return (const OSSCIR_CONST T *)p;
+}
+
+// A pointer loaded from memory is generic (flat loads and stores); the
+// round trip through the global address space lets the compiler use global
+// memory instructions for it.
+template <typename T>
+__device__ __forceinline__ T *as_global(T *p) {
+  return (T *)(__attribute__((address_space(1))) T *)p;
+}
+
+// A copy of *p read word by word through the scalar cache (p uniform over
+// the wave); words the caller never uses are not loaded.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
+  const OSSCIR_CONST int *q = (const OSSCIR_CONST int *)p;
+  T out;
+  int *o = reinterpret_cast<int *>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = q[i];
+  return out;
+}
+
 }  // namespace osscir

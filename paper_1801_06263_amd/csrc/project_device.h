@@ -219,7 +219,7 @@ __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, 
           have_next = (!WIDE || vn.d1 - vn.d0 + 1 <= kBpMaxBins) && sb <= vn.d1 - vn.d0;
           if (have_next) bin_load<NCH>(rays, q, q_stride, (unsigned)(v + 1) * nb + (unsigned)(vn.d0 + sb), nxt);
         }
-        const ViewGeom vg = sd.views[v];
+        const ViewGeom vg = load_uniform(sd.views + v);
         int dlo, dhi;
         pixel_bins(sd, vg, vt, X, Y, dlo, dhi);
         const double dx = vg.sx - fx;

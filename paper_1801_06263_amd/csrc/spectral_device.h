@@ -36,9 +36,9 @@ __device__ __forceinline__ void energy_sums(const ScanDesc &sd, float p0, float 
 #pragma unroll
     for (int j = 0; j < kWin * 6; ++j) hb[j] = 0.0f;
   }
-  const float *__restrict__ tab = sd.tab;
+  const OSSCIR_CONST float *tab = as_const(sd.tab);
   for (int i = 0; i < sd.n_energy; ++i) {
-    const float *t = tab + i * kTab;
+    const OSSCIR_CONST float *t = tab + i * kTab;
     float E, E1, E2;
     if (SHIFT) {
       const float zs = __fmaf_rn(t[kTabMu + 2], p2, __fmaf_rn(t[kTabMu + 1], p1, __fmaf_rn(t[kTabMu], p0, -zshift)));
@@ -72,7 +72,7 @@ __device__ __forceinline__ float energy_sums_safe(const ScanDesc &sd, float p0, 
   if (gmin >= 1e-30f) return 1.0f;
   float zmin = 3.0e38f;
   for (int i = 0; i < sd.n_energy; ++i) {
-    const float *t = sd.tab + i * kTab;
+    const OSSCIR_CONST float *t = as_const(sd.tab) + i * kTab;
     zmin = fminf(zmin, __fmaf_rn(t[kTabMu + 2], p2, __fmaf_rn(t[kTabMu + 1], p1, t[kTabMu] * p0)));
   }
   if (!(zmin > 0.0f)) return 1.0f;  // some energy on the linear branch: no underflow possible
