@@ -64,12 +64,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", default="24,72", help="view-subset sizes of the oracle sample")
     ap.add_argument("--json-out", default=None)
-    ap.add_argument("--legs", default="single,batched",
+    ap.add_argument("--legs", default="single,batched,serving",
                     help="comma list of single (the 512^2 iteration rate), batched; a run without "
                          "'single' prints only the other legs (for profiling)")
     ap.add_argument("--batch-iters", type=int, default=100,
                     help="iterations per slice of the batched leg (0 skips it)")
     ap.add_argument("--batch-per-size", type=int, default=6, help="slices per size in the batched mix")
+    ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=3.0, help="Poisson arrival rate of the serving leg (1/s)")
+    ap.add_argument("--serve-tick", type=int, default=5, help="iterations between admissions and retirements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) to calibrate HBM byte counters")
     return ap.parse_args()
@@ -233,6 +236,76 @@ def batched_leg(n_iter: int, per_size: int):
     }
 
 
+SERVE_TOL = 1e-4
+
+
+def serving_leg(n_requests: int, rate: float, per_tick: int, batch_cfg=None, seed: int = 4242):
+    """Poisson arrivals (rate per second) of reconstruction requests, each a
+    slice of the mixed-size scans (128^2 .. 512^2 uniformly) with its own
+    phantom, an iteration budget uniform in [100, 1000] and the relative
+    change stop 1e-4.  Served twice on the same arrival times: continuous
+    batching (32 slots, 64 GB HBM budget, graph replay, tuned launch shapes)
+    and the plain one-scan-at-a-time loop (one slot, first come first
+    served).  Latency = completion - arrival; solves/s = requests /
+    makespan.  Results are compared bit for bit."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1801_06263_amd import Params, Plan
+    from paper_1801_06263_amd.serve import Request, Server, latency_summary
+
+    rng = np.random.default_rng(seed)
+    tmp_plans = {}
+    reqs, t = [], 0.0
+    for i in range(n_requests):
+        size = int(rng.choice(synth.BATCH_SIZES))
+        pr = synth.batch_slice(size, 1000 + i)
+        if size not in tmp_plans:
+            tmp_plans[size] = (pr.geom, pr.spec, Plan(pr.geom, pr.spec))
+        c = library_counts(tmp_plans[size][2], pr).cpu().numpy()
+        t += float(rng.exponential(1.0 / rate))
+        reqs.append(Request(i, pr.geom, pr.spec, c, BATCH_LAM, max_iter=int(rng.integers(100, 1001)), tol=SERVE_TOL,
+                            arrival=t))
+    scans = [(g, sp) for g, sp, _ in tmp_plans.values()]
+    for _, _, p in tmp_plans.values():
+        p.close()
+    modes = Params(BATCH_LAM, "block", "clip", True)
+    out, finals = {}, {}
+    for name, slots in (("batched", 32), ("sequential", 1)):
+        srv = Server(modes, max_slots=slots, hbm_budget=64 << 30, iters_per_tick=per_tick)
+        if batch_cfg and slots > 1:
+            srv.batch.set_config(**batch_cfg)
+        for g, sp in scans:
+            srv.preload_plan(g, sp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = srv.run(reqs)
+        makespan = time.perf_counter() - t0
+        summ = latency_summary(res, makespan)
+        summ["slots"] = slots
+        summ["peak_hbm_gb"] = round(srv.peak_used / 1e9, 3)
+        summ["ticks"] = srv.ticks
+        out[name] = summ
+        finals[name] = {r.rid: r for r in res}
+        srv.close()
+        print(f"[bench] serving {name}: {summ}", file=sys.stderr, flush=True)
+    b, q = finals["batched"], finals["sequential"]
+    equal = all(torch.equal(b[i].f, q[i].f) and b[i].iters == q[i].iters for i in b)
+    it = np.array([r.iters for r in b.values()])
+    return {
+        "arrival_rate_per_s": rate, "requests": n_requests, "iters_per_tick": per_tick,
+        "stop_rule": f"budget uniform [100, 1000] or relative change <= {SERVE_TOL}",
+        "iterations_per_request": {"min": int(it.min()), "median": int(np.median(it)), "max": int(it.max())},
+        "stopped_by_tolerance": int(sum(1 for r in b.values() if r.rel_change <= SERVE_TOL)),
+        "batched": out["batched"], "sequential": out["sequential"],
+        "solves_per_s_speedup": round(out["batched"]["solves_per_s"] / out["sequential"]["solves_per_s"], 3),
+        "p99_latency_ratio_seq_over_batched": round(out["sequential"]["p99_latency_s"]
+                                                    / out["batched"]["p99_latency_s"], 3),
+        "bitwise_equal_batched_vs_sequential": equal,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -254,6 +327,9 @@ def main():
         line = {}
         if "batched" in legs:
             line["batched"] = batched_leg(args.batch_iters, args.batch_per_size)
+        if "serving" in legs:
+            cfg = line.get("batched", {}).get("tuned_config")
+            line["serving"] = serving_leg(args.serve_requests, args.serve_rate, args.serve_tick, cfg)
         print(json.dumps(line), flush=True)
         return
     pr = synth.problem(args.workload)
@@ -371,6 +447,11 @@ def main():
               file=sys.stderr, flush=True)
         line["batched"] = batched_leg(args.batch_iters, args.batch_per_size)
         print(f"[bench] batched: {line['batched']}", file=sys.stderr, flush=True)
+    if "serving" in legs and args.serve_requests > 0:
+        print(f"[bench] serving leg: {args.serve_requests} requests at {args.serve_rate}/s", file=sys.stderr,
+              flush=True)
+        cfg = line.get("batched", {}).get("tuned_config")
+        line["serving"] = serving_leg(args.serve_requests, args.serve_rate, args.serve_tick, cfg)
     if not args.no_cpu_baseline:
         views = [int(v) for v in args.cpu_views.split(",")]
         print(f"[bench] cpu baseline: oracle on {views}-view subsets", file=sys.stderr, flush=True)

@@ -405,7 +405,7 @@ int osscir_batch_set_slot(osscir_batch b, int32_t slot, osscir_plan plan, const 
   SlotStatus st{};
   st.state = kSlotRunning;
   st.max_iter = max_iter;
-  st.tol = (float)tol;
+  st.tol = tol;
   st.rel_change = 1.0;
   b->init_status[slot] = st;
   b->status_pending[slot] = 1;
@@ -546,7 +546,7 @@ int osscir_batch_tune(osscir_batch b, int32_t iters_per_trial, osscir_batch_conf
   // during the trials the running slots run without a stopping rule
   std::vector<SlotStatus> trial = saved;
   for (SlotStatus &s : trial)
-    if (s.state == kSlotRunning) s.max_iter = 0, s.tol = 0.0f;
+    if (s.state == kSlotRunning) s.max_iter = 0, s.tol = 0.0;
   for (hipEvent_t &e : ev)
     if (hipEventCreate(&e) != hipSuccess) return cleanup(), fail(OSSCIR_EDEVICE, "tune: event creation");
   if (hipEventCreate(&ev_end) != hipSuccess) return cleanup(), fail(OSSCIR_EDEVICE, "tune: event creation");

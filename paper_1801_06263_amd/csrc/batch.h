@@ -35,9 +35,9 @@ struct SlotStatus {
   int state;
   int iters;
   int max_iter;
-  float tol;
+  int pad;
+  double tol;
   double rel_change;  // ||f_{n+1} - f_n|| / ||f_{n+1}|| of the last iteration
-  double pad;
 };
 
 // A work list of one stage.  buf[0..7]: items per XCD; buf[kListHeader +

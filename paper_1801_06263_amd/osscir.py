@@ -256,10 +256,12 @@ class Plan:
         return sigma, img
 
     def new_state(self, c, f0=None):
-        """Device state for MOCCA from counts c [4, V, D] (f0 = fbar0 = f0 or 0, y0 = 0)."""
+        """Device state for MOCCA from counts c [4, V, D] (a tensor or a host
+        array; f0 = fbar0 = f0 or 0, y0 = 0)."""
         import torch
         f = torch.zeros(3, self.n, self.n, dtype=torch.float32, device="cuda") if f0 is None \
             else f0.to(device="cuda", dtype=torch.float32).contiguous().clone()
+        c = torch.as_tensor(np.ascontiguousarray(c, dtype=np.float32)) if isinstance(c, np.ndarray) else c
         return State(f=f, fbar=f.clone(), y=torch.zeros(4, *self.sino_shape, dtype=torch.float32, device="cuda"),
                      c=c.to(device="cuda", dtype=torch.float32).contiguous(), work=self.workspace())
 

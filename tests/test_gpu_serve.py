@@ -1,0 +1,97 @@
+"""Serving on the GPU: each request's result is the same alone and in the mix
+(bit for bit: every slot of a batch computes exactly what the single-scan
+path computes), under continuous batching with staggered arrivals, under an
+HBM budget that limits concurrency, and in the one-slot sequential loop."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def reqs():
+    """Eight requests over three scan shapes: iteration budgets and, for two,
+    a relative-change tolerance; arrivals 20 ms apart."""
+    from paper_1801_06263_amd import Plan
+    from paper_1801_06263_amd.serve import Request
+    probs = [synth.batch_slice(128, 100 + i) for i in range(4)] + [synth.batch_slice(256, 104 + i) for i in range(2)]
+    tiny = synth.problem("tiny")
+    probs += [tiny, tiny]
+    plans = {}
+    out = []
+    rng = np.random.default_rng(5)
+    for i, pr in enumerate(probs):
+        key = pr.geom
+        if key not in plans:
+            plans[key] = Plan(pr.geom, pr.spec)
+        plan = plans[key]
+        g = pr.geom
+        p = plan.forward_project(torch.as_tensor(pr.f_true.astype(np.float32)).cuda())
+        chat = plan.spectral_model(p, torch.zeros(4, g.n_views, g.n_bins, device="cuda"))["chat"]
+        c = synth.poisson_counts(host(chat), pr.seed + i).astype(np.float32)
+        lam = 3e-7 if pr.name == "tiny" else 2e-8
+        tol = 2e-3 if i in (2, 6) else 0.0
+        out.append(Request(i, pr.geom, pr.spec, c, lam, max_iter=int(rng.integers(15, 40)), tol=tol,
+                           arrival=0.02 * i))
+    return out
+
+
+def run(reqs, **kw):
+    from paper_1801_06263_amd import Params
+    from paper_1801_06263_amd.serve import Server
+    srv = Server(Params(1.0, "block", "clip", True), **kw)
+    try:
+        res = srv.run(reqs)
+    finally:
+        ticks = srv.ticks
+        srv.close()
+    return {r.rid: r for r in res}, ticks
+
+
+def test_same_alone_and_in_the_mix(reqs):
+    mix, _ = run(reqs, max_slots=8, iters_per_tick=4)
+    assert sorted(mix) == [r.rid for r in reqs]
+    for r in reqs:
+        alone, _ = run([r], max_slots=2, iters_per_tick=7)
+        a, m = alone[r.rid], mix[r.rid]
+        assert a.iters == m.iters and a.rel_change == m.rel_change
+        assert torch.equal(a.f, m.f), r.rid
+        assert torch.isfinite(m.f).all()
+        if r.tol == 0.0:
+            assert m.iters == r.max_iter
+        else:
+            assert m.iters <= r.max_iter and (m.rel_change <= r.tol or m.iters == r.max_iter)
+
+
+def test_matches_single_scan_iterations(reqs):
+    from paper_1801_06263_amd import Params, Plan
+    mix, _ = run(reqs[:3], max_slots=4, iters_per_tick=5)
+    for r in reqs[:3]:
+        plan = Plan(r.geom, r.spec)
+        st = plan.new_state(r.counts)
+        plan.mocca_iterate(st, Params(r.lam, "block", "clip", True), mix[r.rid].iters)
+        assert torch.equal(st.f, mix[r.rid].f)
+
+
+def test_budget_and_sequential_loop_give_the_same_results(reqs):
+    from paper_1801_06263_amd.serve import Server, plan_bytes, request_bytes
+    mix, _ = run(reqs, max_slots=8, iters_per_tick=4)
+    seq, _ = run(reqs, max_slots=1, iters_per_tick=4)
+    # room for the plans and about two of the largest requests at a time
+    geoms = {r.geom for r in reqs}
+    big = max(request_bytes(g, Server._estimate_workspace(g)) for g in geoms)
+    budget = sum(plan_bytes(g) for g in geoms) + 2 * big + 1
+    tight, _ = run(reqs, max_slots=8, iters_per_tick=4, hbm_budget=budget)
+    for r in reqs:
+        assert torch.equal(mix[r.rid].f, seq[r.rid].f) and torch.equal(mix[r.rid].f, tight[r.rid].f), r.rid
+    lat_seq = max(x.latency for x in seq.values())
+    lat_mix = max(x.latency for x in mix.values())
+    print(f"max latency: batched {lat_mix:.3f}s, sequential {lat_seq:.3f}s")
