@@ -71,7 +71,7 @@ def parse():
                     help="iterations per slice of the batched leg (0 skips it)")
     ap.add_argument("--batch-per-size", type=int, default=6, help="slices per size in the batched mix")
     ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving leg (0 skips it)")
-    ap.add_argument("--serve-rate", type=float, default=3.0, help="Poisson arrival rate of the serving leg (1/s)")
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrival rate of the serving leg (1/s)")
     ap.add_argument("--serve-tick", type=int, default=5, help="iterations between admissions and retirements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) to calibrate HBM byte counters")
