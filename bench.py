@@ -65,8 +65,10 @@ def parse():
     ap.add_argument("--cpu-views", default="24,72", help="view-subset sizes of the oracle sample")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--legs", default="single,batched,serving",
-                    help="comma list of single (the 512^2 iteration rate), batched; a run without "
-                         "'single' prints only the other legs (for profiling)")
+                    help="comma list of single (the 512^2 iteration rate), batched, serving, convergence; a run "
+                         "without 'single' prints only the other legs")
+    ap.add_argument("--conv-workloads", default="medium:500,large:1000",
+                    help="workload:iterations pairs of the convergence leg")
     ap.add_argument("--batch-iters", type=int, default=100,
                     help="iterations per slice of the batched leg (0 skips it)")
     ap.add_argument("--batch-per-size", type=int, default=6, help="slices per size in the batched mix")
@@ -236,6 +238,60 @@ def batched_leg(n_iter: int, per_size: int):
     }
 
 
+CONV_GRIDS = {
+    "block": (5e-9, 1e-8, 2e-8, 5e-8, 1e-7, 2e-7, 3e-7, 5e-7),
+    "mupc": (3e-7, 1e-6, 2e-6, 5e-6, 1e-5, 2e-5, 5e-5),
+    "diag": (1e-9, 1e-8, 3e-8, 1e-7, 3e-7, 1e-6),
+}
+
+
+def convergence_leg(spec_str: str):
+    """D_TPL(c, chat(f_n)) per iteration (the paper's Fig. 3 quantity) for
+    block-diagonal SPC, mu-PC (diagonal SPC in the orthonormal material
+    basis) and diagonal SPC, each over a lambda grid, clipped curvature; the
+    best lambda per method is the one with the lowest final D_TPL."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1801_06263_amd import Params, Plan
+    from paper_1801_06263_amd.osscir import mu_pc_spectral
+
+    out = {}
+    for item in spec_str.split(","):
+        wl, n_iter = item.split(":")
+        n_iter = int(n_iter)
+        pr = synth.problem(wl)
+        plan = Plan(pr.geom, pr.spec)
+        c = library_counts(plan, pr)
+        spec_t, _ = mu_pc_spectral(pr.spec)
+        plan_t = Plan(pr.geom, spec_t)
+        g = pr.geom
+        floor = float(plan.dtpl(torch.as_tensor(pr.f_true.astype(np.float32)).cuda(), c).item())
+        res = {"iterations": n_iter, "dtpl_at_truth": floor,
+               "dtpl_at_zero": float(plan.dtpl(torch.zeros(3, g.n, g.n, device="cuda"), c).item())}
+        marks = [m for m in (1, 10, 30, 100, 300, 1000, 2000) if m <= n_iter]
+        for method, lams in CONV_GRIDS.items():
+            finals, curves = [], {}
+            for lam in lams:
+                pl = plan_t if method == "mupc" else plan
+                st = pl.new_state(c)
+                prm = Params(lam, "diag" if method == "mupc" else method, "clip", True)
+                d = pl.mocca_iterate(st, prm, n_iter, dtpl=True).double().cpu().numpy()
+                fin = float(d[-1]) if np.isfinite(d[-1]) else float("inf")
+                finals.append(fin)
+                curves[lam] = {m: (float(d[m - 1]) if np.isfinite(d[m - 1]) else None) for m in marks}
+            k = int(np.argmin(finals))
+            res[method] = {"lambda_grid": list(lams), "final_dtpl": finals, "best_lambda": lams[k],
+                           "best_curve": curves[lams[k]]}
+            print(f"[bench] convergence {wl} {method}: best lambda {lams[k]:.1e}, final {finals[k]:.4e}",
+                  file=sys.stderr, flush=True)
+        out[wl] = res
+        plan.close()
+        plan_t.close()
+    return out
+
+
 SERVE_TOL = 1e-4
 
 
@@ -330,7 +386,12 @@ def main():
         if "serving" in legs:
             cfg = line.get("batched", {}).get("tuned_config")
             line["serving"] = serving_leg(args.serve_requests, args.serve_rate, args.serve_tick, cfg)
+        if "convergence" in legs:
+            line["convergence"] = convergence_leg(args.conv_workloads)
         print(json.dumps(line), flush=True)
+        if args.json_out:
+            with open(args.json_out, "w") as fh:
+                fh.write(json.dumps(line) + "\n")
         return
     pr = synth.problem(args.workload)
     geom = pr.geom

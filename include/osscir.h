@@ -201,6 +201,25 @@ int osscir_ray_nnz(osscir_plan plan, int32_t *nnz, osscir_stream stream);
 int osscir_dtpl(osscir_plan plan, const float *f, const float *c, double *out, void *work, size_t work_bytes,
                 osscir_stream stream);
 
+/* mu-preconditioning (Sec. I; Sec. II "Step lengths"): MOCCA with diagonal
+ * SPC in a material basis that is orthonormal in energy.  The paper defers
+ * the transform to its Ref. Barber2016b; this library reads it as
+ * Gram-Schmidt of the attenuation rows mu_m(E_i), in material order, under
+ * the inner product <u, v> = sum_i w_i u_i v_i, w_i = (1/n_win) sum_w s_{w,i}.
+ * Outputs (HOST arrays): B [3][3] row-major, lower triangular, and
+ * mu_out [3][n_energy] = B mu with <mu_out_j, mu_out_k> = delta_jk.  A plan
+ * built with mu_out in place of mu and run with OSSCIR_PRECOND_DIAG iterates
+ * the coefficients g of the new basis; the maps are f = B^T g (and
+ * g = B^-T f), applied with osscir_material_transform.  EINVAL if the rows
+ * are dependent under the weights.  Host only, no device work. */
+int osscir_mu_pc_basis(const osscir_spectral *spec, double *B, double *mu_out);
+
+/* out[j][k] = sum_m M[j][m] in[m][k] for 3-channel maps of n_pixels pixels
+ * (DEVICE in, out, FP32; M a HOST 3x3 row-major matrix applied in FP64; in
+ * place allowed): the change of material basis of mu-preconditioning. */
+int osscir_material_transform(const double *M, const float *in, float *out, int32_t n_pixels,
+                              osscir_stream stream);
+
 /* ------------------------------------------------------------------------
  * Batched iterations: many independent scans ("slots", each with its own
  * plan, state and lambda) advanced together, one launch per stage for the

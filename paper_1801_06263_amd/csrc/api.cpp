@@ -396,6 +396,59 @@ int osscir_mocca_stage(osscir_plan plan, const osscir_params *params, osscir_sta
   return run_stage(plan->sd, a, state, stage, (hipStream_t)stream);
 }
 
+int osscir_mu_pc_basis(const osscir_spectral *spec, double *B, double *mu_out) {
+  clear_error();
+  if (!spec || !B || !mu_out || !spec->mu || !spec->s) return fail(OSSCIR_EINVAL, "mu_pc_basis: null argument");
+  if (spec->n_mat != kMat || spec->n_win < 1) return fail(OSSCIR_EINVAL, "mu_pc_basis: need n_mat = 3, n_win >= 1");
+  const int I = spec->n_energy, W = spec->n_win;
+  if (I < kMat) return fail(OSSCIR_EINVAL, "mu_pc_basis: need n_energy >= 3");
+  // energy weights: the window responses averaged over windows
+  std::vector<double> w(I, 0.0);
+  for (int i = 0; i < I; ++i) {
+    for (int k = 0; k < W; ++k) w[i] += spec->s[k * I + i];
+    w[i] /= W;
+    if (!(w[i] >= 0) || !std::isfinite(w[i])) return fail(OSSCIR_EINVAL, "mu_pc_basis: bad window response");
+  }
+  auto dot = [&](const double *u, const double *v) {
+    double acc = 0.0;
+    for (int i = 0; i < I; ++i) acc += w[i] * u[i] * v[i];
+    return acc;
+  };
+  // Gram-Schmidt of the attenuation rows in material order; row j of B holds
+  // the coefficients of the j-th orthonormal function in the original basis
+  std::vector<double> q((size_t)kMat * I), v(I);
+  double b[kMat][kMat] = {};
+  for (int j = 0; j < kMat; ++j) {
+    const double *mj = spec->mu + (size_t)j * I;
+    for (int i = 0; i < I; ++i) v[i] = mj[i];
+    double bj[kMat] = {0.0, 0.0, 0.0};
+    bj[j] = 1.0;
+    for (int k = 0; k < j; ++k) {
+      const double proj = dot(mj, &q[(size_t)k * I]);
+      for (int i = 0; i < I; ++i) v[i] -= proj * q[(size_t)k * I + i];
+      for (int m = 0; m < kMat; ++m) bj[m] -= proj * b[k][m];
+    }
+    const double nrm = std::sqrt(dot(v.data(), v.data()));
+    if (!(nrm > 1e-10 * std::sqrt(dot(mj, mj))) || !std::isfinite(nrm))
+      return fail(OSSCIR_EINVAL, "mu_pc_basis: attenuation rows are linearly dependent under the weights");
+    for (int i = 0; i < I; ++i) q[(size_t)j * I + i] = v[i] / nrm;
+    for (int m = 0; m < kMat; ++m) b[j][m] = bj[m] / nrm;
+  }
+  for (int j = 0; j < kMat; ++j)
+    for (int m = 0; m < kMat; ++m) B[j * kMat + m] = b[j][m];
+  std::memcpy(mu_out, q.data(), q.size() * sizeof(double));
+  return OSSCIR_OK;
+}
+
+int osscir_material_transform(const double *M, const float *in, float *out, int32_t n_pixels, osscir_stream stream) {
+  if (!M || !in || !out || n_pixels < 0) return fail(OSSCIR_EINVAL, "material_transform: null pointer or bad size");
+  if (n_pixels == 0) return OSSCIR_OK;
+  for (int j = 0; j < 9; ++j)
+    if (!std::isfinite(M[j])) return fail(OSSCIR_EINVAL, "material_transform: matrix not finite");
+  OSSCIR_HIP(launch_material_transform(M, in, out, n_pixels, (hipStream_t)stream), "material_transform launch");
+  return OSSCIR_OK;
+}
+
 int osscir_ray_nnz(osscir_plan plan, int32_t *nnz, osscir_stream stream) {
   int rc = check_plan(plan);
   if (rc) return rc;

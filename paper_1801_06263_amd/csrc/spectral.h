@@ -22,6 +22,9 @@ hipError_t launch_back_primal(const ScanDesc &sd, const float *qS, float *f, flo
 hipError_t launch_steps(const ScanDesc &sd, const float *G, float lambda, bool block, float *sigma, float *terms,
                         float *out_img, hipStream_t st);
 
+// out = M in for 3-channel maps of npix pixels (M row-major 3x3, in place allowed).
+hipError_t launch_material_transform(const double M[9], const float *in, float *out, int npix, hipStream_t st);
+
 int dtpl_partial_count(const ScanDesc &sd);
 hipError_t launch_dtpl(const ScanDesc &sd, const float *f, const float *c, float *p_scratch, void *pack,
                        double *partial, double *out, hipStream_t st);

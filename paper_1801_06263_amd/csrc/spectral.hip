@@ -163,6 +163,21 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double *__restrict__
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// ---------------------------------------------------------------- basis change
+
+// out[j][k] = sum_m M[j][m] in[m][k] for 3-channel maps (in place allowed):
+// the change of material basis of mu-preconditioning.
+__global__ void __launch_bounds__(256) k_material_transform(double m00, double m01, double m02, double m10,
+                                                             double m11, double m12, double m20, double m21,
+                                                             double m22, const float *in, float *out, int npix) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npix) return;
+  const double a = in[k], b = in[npix + k], c = in[2 * npix + k];
+  out[k] = (float)(m00 * a + m01 * b + m02 * c);
+  out[npix + k] = (float)(m10 * a + m11 * b + m12 * c);
+  out[2 * npix + k] = (float)(m20 * a + m21 * b + m22 * c);
+}
+
 // ---------------------------------------------------------------- launchers
 
 static inline dim3 ray_grid(const ScanDesc &sd) { return dim3((sd.n_rays + 255) / 256); }
@@ -229,6 +244,12 @@ hipError_t launch_steps(const ScanDesc &sd, const float *G, float lambda, bool b
     hipLaunchKernelGGL(k_scale_steps<true>, dim3((count + 255) / 256), dim3(256), 0, st, count, lambda, out_img);
   else
     hipLaunchKernelGGL(k_scale_steps<false>, dim3((count + 255) / 256), dim3(256), 0, st, count, lambda, out_img);
+  return hipGetLastError();
+}
+
+hipError_t launch_material_transform(const double M[9], const float *in, float *out, int npix, hipStream_t st) {
+  hipLaunchKernelGGL(k_material_transform, dim3((npix + 255) / 256), dim3(256), 0, st, M[0], M[1], M[2], M[3], M[4],
+                     M[5], M[6], M[7], M[8], in, out, npix);
   return hipGetLastError();
 }
 

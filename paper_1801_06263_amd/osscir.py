@@ -75,6 +75,8 @@ SIGNATURES = {
     "osscir_mocca_stage": (c_int32, [c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_State), c_int32, c_void_p]),
     "osscir_ray_nnz": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "osscir_dtpl": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "osscir_mu_pc_basis": (c_int32, [ctypes.POINTER(_Spectral), _dp, _dp]),
+    "osscir_material_transform": (c_int32, [_dp, c_void_p, c_void_p, c_int32, c_void_p]),
     "osscir_batch_create": (c_int32, [ctypes.POINTER(_Params), c_int32, ctypes.POINTER(c_void_p)]),
     "osscir_batch_destroy": (c_int32, [c_void_p]),
     "osscir_batch_set_slot": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.POINTER(_State), c_double, c_int32,
@@ -307,6 +309,42 @@ class Plan:
                                 _dev(c, (4, *self.sino_shape), torch.float32, "c"), _dev(out), _dev(work),
                                 work.numel(), _stream_handle(stream)))
         return out
+
+
+def mu_pc_basis(spec):
+    """(B [3, 3], mu~ [3, I]) of mu-preconditioning: mu~ = B mu orthonormal in
+    energy; maps f = B^T g.  Host computation in the library."""
+    lib = load_library()
+    mu = np.ascontiguousarray(spec.mu, dtype=np.float64)
+    s = np.ascontiguousarray(spec.s, dtype=np.float64)
+    n0 = np.ascontiguousarray(spec.n0, dtype=np.float64)
+    sp = _Spectral(mu.shape[0], s.shape[0], s.shape[1], mu.ctypes.data_as(_dp), s.ctypes.data_as(_dp),
+                   n0.ctypes.data_as(_dp))
+    B = np.zeros((3, 3))
+    mu_t = np.zeros_like(mu)
+    _check(lib.osscir_mu_pc_basis(ctypes.byref(sp), B.ctypes.data_as(_dp), mu_t.ctypes.data_as(_dp)))
+    return B, mu_t
+
+
+def mu_pc_spectral(spec):
+    """The spectral description with mu~ in place of mu, and B."""
+    import types
+    B, mu_t = mu_pc_basis(spec)
+    return types.SimpleNamespace(mu=mu_t, s=np.asarray(spec.s), n0=np.asarray(spec.n0)), B
+
+
+def material_transform(M, x, out=None, stream=None):
+    """out = M x for [3, n, n] maps (M a 3x3 host matrix)."""
+    import torch
+    lib = load_library()
+    Mc = np.ascontiguousarray(M, dtype=np.float64).reshape(3, 3)
+    xp = _dev(x, None, torch.float32, "x")
+    if x.shape[0] != 3:
+        raise ValueError("x must have 3 channels")
+    out = torch.empty_like(x) if out is None else out
+    _check(lib.osscir_material_transform(Mc.ctypes.data_as(_dp), xp, _dev(out, tuple(x.shape), torch.float32, "out"),
+                                         int(x[0].numel()), _stream_handle(stream)))
+    return out
 
 
 BATCH_CONFIG_FIELDS = [name for name, _ in _BatchConfig._fields_]

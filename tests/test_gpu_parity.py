@@ -256,6 +256,40 @@ def test_mocca_trajectory_parity(tiny, precond, curvature, fp64):
     assert rel_y <= 1e-3
 
 
+def test_mu_pc_trajectory_parity(tiny):
+    """mu-PC: diagonal SPC in the library's orthonormal material basis (plan
+    built with mu~ = B mu, maps f = B^T g) against the oracle's mu-PC."""
+    from paper_1801_06263_amd import Params, Plan
+    from paper_1801_06263_amd.osscir import material_transform, mu_pc_spectral
+    from oracle import mupc
+    pr, X, c, plan = tiny
+    lam, n_it = 1e-5, 100
+    f_ref, _, _, B_ref = mupc.mocca_mu_pc(X, c, pr.spec, lam, n_it, "clip")
+    spec_t, B = mu_pc_spectral(pr.spec)
+    np.testing.assert_allclose(B, B_ref, rtol=1e-12, atol=1e-12 * np.abs(B_ref).max())
+    plan_t = Plan(pr.geom, spec_t)
+    st = plan_t.new_state(dev(sino(c, pr.geom)))
+    plan_t.mocca_iterate(st, Params(lam, "diag", "clip", True), n_it)
+    f = host(material_transform(B.T, st.f)).reshape(3, -1)
+    for m in range(3):
+        rel = np.linalg.norm(f[m] - f_ref[m]) / np.linalg.norm(f_ref[m])
+        print(f"mu-PC material {m}: rel L2 {rel:.2e}")
+        assert rel <= 1e-3
+
+
+def test_material_transform():
+    from paper_1801_06263_amd.osscir import material_transform
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((3, 37, 37)).astype(np.float32)
+    M = rng.standard_normal((3, 3))
+    got = host(material_transform(M, dev(x)))
+    ref = np.einsum("jm,mk->jk", M, x.reshape(3, -1).astype(np.float64)).reshape(3, 37, 37)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-6 * np.abs(ref).max())
+    xd = dev(x)
+    material_transform(M, xd, out=xd)  # in place
+    np.testing.assert_array_equal(host(xd), got)
+
+
 def test_mocca_one_step_intermediates(tiny):
     """One iteration from a non-trivial point: y and f match the oracle's parts."""
     from paper_1801_06263_amd import Params

@@ -371,3 +371,70 @@ def test_claim_block_spc_beats_diagonal_spc(micro):
                 vals.append(np.inf)
         best[pre] = min(vals)
     assert best["block"] < 0.1 * best["diag"]
+
+
+# ------------------------------------------------------------ mu-PC (reading R16)
+
+from oracle import mupc  # noqa: E402
+
+
+def test_mupc_basis_is_weighted_gram_schmidt():
+    """mu~ = B mu is orthonormal under <u, v> = sum_i w_i u_i v_i, B is lower
+    triangular with a positive diagonal, and Gram-Schmidt in material order
+    equals the inverse Cholesky factor of the weighted Gram matrix."""
+    spec = synth.make_spectral(20, 119, 120.0, 1e5)
+    B, Q = mupc.mu_pc_basis(spec)
+    w = mupc.energy_weights(spec)
+    assert abs(w.sum() - 1.0) < 1e-12 and (w >= 0).all()
+    np.testing.assert_allclose((Q * w) @ Q.T, np.eye(3), atol=1e-12)
+    np.testing.assert_allclose(Q, B @ spec.mu, atol=1e-12 * np.abs(Q).max())
+    assert np.all(np.triu(B, 1) == 0) and np.all(np.diag(B) > 0)
+    gram = (spec.mu * w) @ spec.mu.T
+    np.testing.assert_allclose(B, np.linalg.inv(np.linalg.cholesky(gram)), atol=1e-10 * np.abs(B).max())
+    # a basis orthonormalised without the spectral weights is not orthonormal under them
+    _, Q_unw = mupc.mu_pc_basis(synth.Spectral(mu=spec.mu, s=np.ones_like(spec.s) / spec.s.shape[1], n0=spec.n0))
+    assert np.abs((Q_unw * w) @ Q_unw.T - np.eye(3)).max() > 1e-2
+
+
+def test_mupc_counts_model_is_basis_invariant(micro):
+    geom, spec, f_true, X, c = micro
+    spec_t, B = mupc.transformed_spectral(spec)
+    rng = np.random.default_rng(7)
+    g = rng.random((3, X.shape[1])) * 0.1
+    f = mupc.maps_from_basis(g, B)
+    np.testing.assert_allclose(model.counts_model(X @ g.T, spec_t), model.counts_model(X @ f.T, spec), rtol=1e-11)
+    np.testing.assert_allclose(mupc.basis_from_maps(f, B), g, atol=1e-12)
+
+
+def test_mupc_truth_is_a_fixed_point(micro):
+    geom, spec, f_true, X, c = micro
+    f, st, _, _ = mupc.mocca_mu_pc(X, c, spec, 1e-5, 5, "clip", f0=f_true)
+    np.testing.assert_allclose(f, f_true, atol=1e-10)
+    assert np.abs(st.y).max() < 1e-6
+
+
+def test_claim_block_and_mupc_beat_diag(micro):
+    """Sec. III, Fig. 3: with lambda tuned per method, block-diagonal SPC and
+    mu-PC both end far below diagonal SPC in D_TPL.  (The paper also finds
+    block SPC ahead of mu-PC; on this 16^2 problem under this reading of
+    mu-PC the two are within a factor of two of each other and their order
+    depends on the lambda grid, so the order is not asserted.)"""
+    geom, spec, f_true, X, c = micro
+    grids = {"block": (1e-7, 2e-7, 3e-7, 4e-7), "mupc": (3e-6, 6e-6, 1e-5, 1.5e-5, 2e-5),
+             "diag": (1e-7, 3e-7, 1e-6)}
+    best = {}
+    for name, lams in grids.items():
+        vals = []
+        for lam in lams:
+            try:
+                if name == "mupc":
+                    _, _, hist, _ = mupc.mocca_mu_pc(X, c, spec, lam, 100, "clip", dtpl_every=100)
+                else:
+                    _, hist = mocca.mocca(X, c, spec, lam, 100, name, "clip", dtpl_every=100)
+                d = hist[-1][1]
+                vals.append(d if np.isfinite(d) else np.inf)
+            except np.linalg.LinAlgError:
+                vals.append(np.inf)
+        best[name] = min(vals)
+    print(best)
+    assert max(best["block"], best["mupc"]) < 0.1 * best["diag"]
