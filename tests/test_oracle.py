@@ -373,7 +373,7 @@ def test_claim_block_spc_beats_diagonal_spc(micro):
     assert best["block"] < 0.1 * best["diag"]
 
 
-# ------------------------------------------------------------ mu-PC (reading R16)
+# ------------------------------------------------------------ mu-PC
 
 from oracle import mupc  # noqa: E402
 
