@@ -4,11 +4,10 @@ that is orthonormal in X-ray energy (Sec. I; Sec. II "Step lengths"), FP64.
 TEST INFRASTRUCTURE ONLY: imported by tests/, __graft_entry__.smoke() and
 bench.py's CPU baseline; never by the library or its binding.
 
-The paper states what mu-PC does -- the materials expansion set is
-transformed to an orthogonal set of functions of energy, and the diagonal
-step lengths are computed the same way with K(f0) evaluated in the
-transformed basis -- and defers the transform itself to its Ref.
-Barber2016b.  Reading taken here:
+The paper describes mu-PC as a change of material basis to attenuation
+curves that are mutually orthogonal over energy, with diagonal SPC's step
+lengths formed from K(f0) in the new basis, and leaves the transform itself
+to its Ref. Barber2016b.  Reading taken here:
 
   * inner product over energy bins  <u, v> = sum_i w_i u_i v_i  with
     w_i = (1/W) sum_w s_{w,i}, the detected spectrum averaged over windows;
