@@ -77,14 +77,18 @@ typedef struct {
 } osscir_geometry;
 
 /* Spectral tables of Eq. (fullModel), HOST pointers, copied at plan creation:
- * mu [n_mat][n_energy] (cm^-1 per unit material fraction), s [n_win][n_energy]
- * (each row >= 0 and summing to 1), n0 [n_win] incident photons per ray.
+ * mu [n_mat][n_energy] (cm^-1 per unit material fraction) and n_resp sets of
+ * window responses s [n_resp][n_win][n_energy] (each row >= 0 and summing
+ * to 1) with incident photons per ray n0 [n_resp][n_win].  n_resp = 0 or 1:
+ * one response shared by every ray; n_resp = n_bins: one per detector bin d
+ * (the same in every view), the calibrated per-pixel spectra of Sec. III.
  * Supported: n_mat = 3, n_win = 4, 1 <= n_energy <= 512. */
 typedef struct {
   int32_t n_mat, n_win, n_energy;
   const double *mu;
   const double *s;
   const double *n0;
+  int32_t n_resp;
 } osscir_spectral;
 
 /* Step-size ratio lambda > 0 (Sec. II: "a step size ratio parameter that must
@@ -211,7 +215,8 @@ int osscir_dtpl(osscir_plan plan, const float *f, const float *c, double *out, v
  * built with mu_out in place of mu and run with OSSCIR_PRECOND_DIAG iterates
  * the coefficients g of the new basis; the maps are f = B^T g (and
  * g = B^-T f), applied with osscir_material_transform.  EINVAL if the rows
- * are dependent under the weights.  Host only, no device work. */
+ * are dependent under the weights or the responses are per detector bin
+ * (n_resp > 1).  Host only, no device work. */
 int osscir_mu_pc_basis(const osscir_spectral *spec, double *B, double *mu_out);
 
 /* out[j][k] = sum_m M[j][m] in[m][k] for 3-channel maps of n_pixels pixels

@@ -93,7 +93,7 @@ def mocca_step(X, rho, state: State, c, spec, lam: float, precond: str = "block"
     # expansion point f0 = fbar_n
     p = X @ state.fbar.T                                  # [L, M]
     A, B, g = model.matrices_AB(p, spec)
-    chat = spec.n0[None, :] * g                           # Eq. (finalModel)
+    chat = model.incident(spec) * g                       # Eq. (finalModel)
     r = model.residual(c, chat)
     G = model.ray_jacobian_from_A(A, spec)                # K(f0) per ray, [L, W, M]
     if curvature == "clip":

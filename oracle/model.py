@@ -2,7 +2,9 @@
 
 Arrays are ray-major: p [L, M] material line integrals (X f_m)_l, counts and
 residuals [L, W].  The spectral tables come from ``synth.Spectral``:
-mu [M, I], s [W, I] (rows sum to one, shared by all rays), n0 [W].
+mu [M, I], s [W, I] (rows sum to one, shared by all rays), n0 [W]; or from
+``synth.RaySpectral`` with a response per ray, s [L, W, I] and n0 [L, W]
+(the paper's per-detector-pixel spectra).
 
 Pinned by: zero attenuation (window totals chat = N, A = B = s), the
 monochromatic Beer-Lambert case, central finite differences of D_TPL for the
@@ -37,16 +39,33 @@ def energy_line_integrals(p, mu):
     return np.asarray(p, dtype=np.float64) @ mu
 
 
+def per_ray(spec) -> bool:
+    return np.ndim(spec.s) == 3
+
+
+def incident(spec):
+    """N as [L or 1, W]."""
+    n0 = np.asarray(spec.n0, dtype=np.float64)
+    return n0 if n0.ndim == 2 else n0[None, :]
+
+
+def window_sums(e, spec):
+    """sum_i s_{w,i} e_{l,i} -> [L, W] (s shared or per ray)."""
+    if per_ray(spec):
+        return np.einsum("li,lwi->lw", e, spec.s)
+    return e @ spec.s.T
+
+
 def counts_model(p, spec):
     """chat_{w,l} of Eq. (finalModel): N_w sum_i s_{w,i} softexp(-(Zf)_{l,i})."""
     z = energy_line_integrals(p, spec.mu)
-    return spec.n0[None, :] * (softexp(-z) @ spec.s.T)
+    return incident(spec) * window_sums(softexp(-z), spec)
 
 
 def counts_model_standard(p, spec):
     """chat of Eq. (fullModel), plain exp (equal to Eq. finalModel when Zf >= 0)."""
     z = energy_line_integrals(p, spec.mu)
-    return spec.n0[None, :] * (np.exp(-z) @ spec.s.T)
+    return incident(spec) * window_sums(np.exp(-z), spec)
 
 
 def dtpl_terms(c, chat):
@@ -73,9 +92,10 @@ def matrices_AB(p, spec):
     A[l, w, i] = s_{w,i} softexp'(-(Zf)_{l,i}) / sum_i' s_{w,i'} softexp(-(Zf)_{l,i'})
     and B with softexp'' in the numerator, plus g[l, w] (the denominator)."""
     z = energy_line_integrals(p, spec.mu)
-    g = softexp(-z) @ spec.s.T                                   # [L, W]
-    A = spec.s[None, :, :] * softexp_d1(-z)[:, None, :] / g[:, :, None]
-    B = spec.s[None, :, :] * softexp_d2(-z)[:, None, :] / g[:, :, None]
+    g = window_sums(softexp(-z), spec)                           # [L, W]
+    S = spec.s if per_ray(spec) else spec.s[None, :, :]
+    A = S * softexp_d1(-z)[:, None, :] / g[:, :, None]
+    B = S * softexp_d2(-z)[:, None, :] / g[:, :, None]
     return A, B, g
 
 
@@ -93,14 +113,14 @@ def gradient_p(p, c, spec):
     """Per-ray gradient of L_TPL in p-space: (A mu^T)^T r  (the p_l part of
     Z^T A^T r; the image gradient is X^T of it)."""
     A, _, g = matrices_AB(p, spec)
-    r = residual(c, spec.n0[None, :] * g)
+    r = residual(c, incident(spec) * g)
     return np.einsum("lwi,mi,lw->lm", A, spec.mu, r)
 
 
 def hessian_from_AB(A, B, g, c, spec):
     """Per-ray Hessian of L_TPL in p-space, the ray-l block of
     -Z^T diag(B^T r) Z + Z^T A^T diag(chat + r) A Z (Sec. II), as [L, M, M]."""
-    chat = spec.n0[None, :] * g
+    chat = incident(spec) * g
     r = residual(c, chat)
     btr = np.einsum("lwi,lw->li", B, r)                          # (B^T r)_{l,i}
     term1 = -np.einsum("mi,li,ni->lmn", spec.mu, btr, spec.mu, optimize=True)

@@ -68,6 +68,8 @@ void free_plan(osscir_plan p) {
   if (p->d_rho) (void)hipFree(p->d_rho);
   if (p->d_tab) (void)hipFree(p->d_tab);
   if (p->d_pack) (void)hipFree(p->d_pack);
+  if (p->d_sbin) (void)hipFree(p->d_sbin);
+  if (p->d_n0bin) (void)hipFree(p->d_n0bin);
   delete p;
 }
 
@@ -99,16 +101,23 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   const int I = spec->n_energy;
   if (I < 1 || I > 512) return fail(OSSCIR_EINVAL, "n_energy=%d outside [1, 512]", I);
   if (!spec->mu || !spec->s || !spec->n0) return fail(OSSCIR_EINVAL, "null spectral table");
-  for (int w = 0; w < kWin; ++w) {
-    double sum = 0;
-    for (int i = 0; i < I; ++i) {
-      const double v = spec->s[w * I + i];
-      if (!(v >= 0) || !std::isfinite(v)) return fail(OSSCIR_EINVAL, "s[%d][%d] negative or not finite", w, i);
-      sum += v;
+  const int n_resp = spec->n_resp <= 1 ? 1 : spec->n_resp;
+  if (n_resp != 1 && n_resp != g.n_bins)
+    return fail(OSSCIR_EINVAL, "n_resp=%d must be 0, 1 or n_bins=%d", spec->n_resp, g.n_bins);
+  for (int r = 0; r < n_resp; ++r)
+    for (int w = 0; w < kWin; ++w) {
+      double sum = 0;
+      for (int i = 0; i < I; ++i) {
+        const double v = spec->s[((size_t)r * kWin + w) * I + i];
+        if (!(v >= 0) || !std::isfinite(v))
+          return fail(OSSCIR_EINVAL, "s[%d][%d][%d] negative or not finite", r, w, i);
+        sum += v;
+      }
+      if (std::fabs(sum - 1.0) > 1e-6)
+        return fail(OSSCIR_EINVAL, "row (%d, %d) of s sums to %.9g, not 1", r, w, sum);
+      const double n0 = spec->n0[(size_t)r * kWin + w];
+      if (!(n0 > 0) || !std::isfinite(n0)) return fail(OSSCIR_EINVAL, "n0[%d][%d] must be > 0", r, w);
     }
-    if (std::fabs(sum - 1.0) > 1e-6) return fail(OSSCIR_EINVAL, "row %d of s sums to %.9g, not 1", w, sum);
-    if (!(spec->n0[w] > 0) || !std::isfinite(spec->n0[w])) return fail(OSSCIR_EINVAL, "n0[%d] must be > 0", w);
-  }
   for (int j = 0; j < kMat * I; ++j)
     if (!std::isfinite(spec->mu[j])) return fail(OSSCIR_EINVAL, "mu not finite");
 
@@ -150,12 +159,21 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
       rays[(size_t)v * D + d] = RayLine{nx, ny, (float)a, (float)hmax, (float)kappa, 0.0f};
     }
   }
-  // spectral table
+  // spectral table: shared responses folded with mu, or (per detector bin)
+  // mu and its products here and the responses in a per-bin array
+  const bool per_bin = n_resp > 1;
   std::vector<float> tab((size_t)I * kTab, 0.0f);
+  std::vector<float4> sbin, n0bin;
   for (int i = 0; i < I; ++i) {
     float *t = &tab[(size_t)i * kTab];
     const double mu[3] = {spec->mu[0 * I + i], spec->mu[1 * I + i], spec->mu[2 * I + i]};
     for (int m = 0; m < 3; ++m) t[kTabMu + m] = (float)mu[m];
+    if (per_bin) {
+      int k = 0;
+      for (int m = 0; m < 3; ++m)
+        for (int n = m; n < 3; ++n) t[kTabMuMu + (k++)] = (float)(mu[m] * mu[n]);
+      continue;
+    }
     for (int w = 0; w < kWin; ++w) {
       const double s = spec->s[w * I + i];
       t[kTabS + w] = (float)s;
@@ -165,20 +183,38 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
         for (int n = m; n < 3; ++n) t[kTabSMuMu + 6 * w + (k++)] = (float)(s * mu[m] * mu[n]);
     }
   }
+  if (per_bin) {
+    sbin.resize((size_t)I * D);
+    n0bin.resize(D);
+    for (int d = 0; d < D; ++d) {
+      const double *sd_ = spec->s + (size_t)d * kWin * I;
+      for (int i = 0; i < I; ++i)
+        sbin[(size_t)i * D + d] = make_float4((float)sd_[0 * I + i], (float)sd_[1 * I + i], (float)sd_[2 * I + i],
+                                              (float)sd_[3 * I + i]);
+      const double *n0 = spec->n0 + (size_t)d * kWin;
+      n0bin[d] = make_float4((float)n0[0], (float)n0[1], (float)n0[2], (float)n0[3]);
+    }
+  }
 
   hipError_t e;
   if ((e = hipMalloc(&p->d_rays, rays.size() * sizeof(RayLine))) != hipSuccess ||
       (e = hipMalloc(&p->d_views, views.size() * sizeof(ViewGeom))) != hipSuccess ||
       (e = hipMalloc(&p->d_pack, 2 * (size_t)(N + 2 * kPad) * (N + 2 * kPad) * sizeof(float4))) != hipSuccess ||
       (e = hipMalloc(&p->d_rho, L * sizeof(float))) != hipSuccess ||
-      (e = hipMalloc(&p->d_tab, tab.size() * sizeof(float))) != hipSuccess) {
+      (e = hipMalloc(&p->d_tab, tab.size() * sizeof(float))) != hipSuccess ||
+      (per_bin && (e = hipMalloc(&p->d_sbin, sbin.size() * sizeof(float4))) != hipSuccess) ||
+      (per_bin && (e = hipMalloc(&p->d_n0bin, n0bin.size() * sizeof(float4))) != hipSuccess)) {
     free_plan(p);
     return fail(OSSCIR_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
   if ((e = hipMemcpy(p->d_rays, rays.data(), rays.size() * sizeof(RayLine), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->d_views, views.data(), views.size() * sizeof(ViewGeom), hipMemcpyHostToDevice)) !=
           hipSuccess ||
-      (e = hipMemcpy(p->d_tab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
+      (e = hipMemcpy(p->d_tab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+      (per_bin &&
+       (e = hipMemcpy(p->d_sbin, sbin.data(), sbin.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess) ||
+      (per_bin && (e = hipMemcpy(p->d_n0bin, n0bin.data(), n0bin.size() * sizeof(float4), hipMemcpyHostToDevice)) !=
+                      hipSuccess)) {
     free_plan(p);
     return hip_fail(e, "copying plan tables");
   }
@@ -193,6 +229,9 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   sd.bin_scale = (float)(g.sdd_cm / g.bin_cm);
   sd.cbin = 0.5f * (float)(D - 1);
   for (int w = 0; w < kWin; ++w) sd.n0[w] = (float)spec->n0[w];
+  sd.per_bin = per_bin ? 1 : 0;
+  sd.sbin = p->d_sbin;
+  sd.n0bin = p->d_n0bin;
   // does any 16x16 tile's shadow exceed the back-projector's staging buffer?
   // (the same corner projection the kernel uses, in FP64 with a margin)
   sd.bp_wide = 0;
@@ -400,6 +439,7 @@ int osscir_mu_pc_basis(const osscir_spectral *spec, double *B, double *mu_out) {
   clear_error();
   if (!spec || !B || !mu_out || !spec->mu || !spec->s) return fail(OSSCIR_EINVAL, "mu_pc_basis: null argument");
   if (spec->n_mat != kMat || spec->n_win < 1) return fail(OSSCIR_EINVAL, "mu_pc_basis: need n_mat = 3, n_win >= 1");
+  if (spec->n_resp > 1) return fail(OSSCIR_EINVAL, "mu_pc_basis: needs one shared window response (n_resp <= 1)");
   const int I = spec->n_energy, W = spec->n_win;
   if (I < kMat) return fail(OSSCIR_EINVAL, "mu_pc_basis: need n_energy >= 3");
   // energy weights: the window responses averaged over windows

@@ -32,6 +32,8 @@ __device__ __forceinline__ SlotDesc load_slot(const SlotDesc *slots, int s) {
   d.sd.rays = as_global(q->sd.rays);
   d.sd.rho = as_global(q->sd.rho);
   d.sd.views = as_global(q->sd.views);
+  d.sd.sbin = as_global(q->sd.sbin);
+  d.sd.n0bin = as_global(q->sd.n0bin);
   d.f = as_global(q->f);
   d.fbar = as_global(q->fbar);
   d.y = as_global(q->y);
@@ -75,8 +77,11 @@ __global__ void __launch_bounds__(256) kb_spectral_dual(const SlotDesc *__restri
     const int s = it >> kItemSlotShift, local = it & kItemLocalMask;
     if (!slot_running(status, s)) continue;
     const SlotDesc sl = load_slot(slots, s);
-    spectral_dual_ray<T, CLIP, BLOCK>(sl.sd, sl.p, sl.c, sl.y, sl.qS, sl.lambda,
-                                      local * (int)blockDim.x + (int)threadIdx.x);
+    const int l = local * (int)blockDim.x + (int)threadIdx.x;
+    if (sl.sd.per_bin)
+      spectral_dual_ray<T, CLIP, BLOCK, true>(sl.sd, sl.p, sl.c, sl.y, sl.qS, sl.lambda, l);
+    else
+      spectral_dual_ray<T, CLIP, BLOCK, false>(sl.sd, sl.p, sl.c, sl.y, sl.qS, sl.lambda, l);
   }
 }
 

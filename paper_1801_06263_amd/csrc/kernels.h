@@ -31,6 +31,11 @@ constexpr int kPad = 4;   // zero border of the packed images of the forward pro
 //   [19..42] s_{w,i} mu_{m,i} mu_{n,i}, m <= n (index 19 + 6w + upper(m,n))
 //   [43..47] zero
 constexpr int kTabMu = 0, kTabS = 3, kTabSMu = 7, kTabSMuMu = 19;
+// With per-detector-bin responses the rows hold mu (0..2) and the products
+// mu_{m,i} mu_{n,i}, m <= n (7..12); the responses s_{w,d,i} are a separate
+// float4 array [I][D] (one 16-byte load per lane and energy, coalesced over
+// neighbouring bins).
+constexpr int kTabMuMu = 7;
 
 // Everything a kernel needs to know about one scan.
 struct ScanDesc {
@@ -45,6 +50,9 @@ struct ScanDesc {
   float cbin;        // (n_bins - 1) / 2
   float n0[kWin];    // incident counts per window
   int bp_wide;       // some 16x16-tile shadow exceeds the back-projector's staging buffer
+  int per_bin;       // window responses and incident counts per detector bin
+  const float4 *sbin;   // [I][D] s_{w,d,i} (w = x, y, z, w), per_bin only
+  const float4 *n0bin;  // [D] incident counts per window, per_bin only
   const struct RayLine *rays;  // [L]
   const ViewGeom *views;        // [V]
   const float *rho;     // [L]

@@ -18,6 +18,8 @@ struct osscir_plan_s {
   void *d_pack = nullptr;  // packed-image scratch of the standalone projector calls
   float *d_rho = nullptr;
   float *d_tab = nullptr;
+  float4 *d_sbin = nullptr;   // per-detector-bin responses [I][D]
+  float4 *d_n0bin = nullptr;  // per-detector-bin incident counts [D]
 };
 
 namespace osscir {

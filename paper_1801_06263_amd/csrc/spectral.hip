@@ -12,7 +12,7 @@ namespace osscir {
 
 // ---------------------------------------------------------------- model out
 
-template <typename T>
+template <typename T, bool PB>
 __global__ void __launch_bounds__(256) k_spectral_model(ScanDesc sd, const float *__restrict__ p,
                                                          const float *__restrict__ c, float *__restrict__ chat,
                                                          float *__restrict__ r, float *__restrict__ G,
@@ -20,12 +20,14 @@ __global__ void __launch_bounds__(256) k_spectral_model(ScanDesc sd, const float
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   const int L = sd.n_rays;
   if (l >= L) return;
-  float g[kWin], af[kWin * kMat], hb[kWin * 6];
-  const float scale = energy_sums_safe<true, true>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb);
+  const int d = l % sd.n_bins;
+  float g[kWin], af[kWin * kMat], hb[kWin * 6], n0[kWin];
+  const float scale = energy_sums_safe<true, true, PB>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb, d);
+  ray_n0<PB>(sd, d, n0);
   T a[kWin][kMat], cw[kWin], rg[kWin];
 #pragma unroll
   for (int w = 0; w < kWin; ++w) {
-    const float ch = sd.n0[w] * g[w] * scale;
+    const float ch = n0[w] * g[w] * scale;
     const float rw = c[w * L + l] - ch;
     if (chat) chat[w * L + l] = ch;
     if (r) r[w * L + l] = rw;
@@ -54,11 +56,11 @@ __global__ void __launch_bounds__(256) k_spectral_model(ScanDesc sd, const float
 
 // ---------------------------------------------------------------- dual step
 
-template <typename T, bool CLIP, bool BLOCK>
+template <typename T, bool CLIP, bool BLOCK, bool PB>
 __global__ void __launch_bounds__(256) k_spectral_dual(ScanDesc sd, const float *__restrict__ p,
                                                         const float *__restrict__ c, float *__restrict__ y,
                                                         float *__restrict__ qS, float lambda) {
-  spectral_dual_ray<T, CLIP, BLOCK>(sd, p, c, y, qS, lambda, blockIdx.x * blockDim.x + threadIdx.x);
+  spectral_dual_ray<T, CLIP, BLOCK, PB>(sd, p, c, y, qS, lambda, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------- steps only
@@ -124,6 +126,7 @@ __global__ void __launch_bounds__(256) k_back_primal(ScanDesc sd, const float *_
 
 // ---------------------------------------------------------------- D_TPL
 
+template <bool PB>
 __global__ void __launch_bounds__(256) k_dtpl_partial(ScanDesc sd, const float *__restrict__ p,
                                                        const float *__restrict__ c, double *__restrict__ partial) {
   __shared__ double red[256];
@@ -131,11 +134,13 @@ __global__ void __launch_bounds__(256) k_dtpl_partial(ScanDesc sd, const float *
   const int L = sd.n_rays;
   double term = 0.0;
   if (l < L) {
-    float g[kWin];
-    energy_sums<false, false>(sd, p[l], p[L + l], p[2 * L + l], g, nullptr, nullptr);
+    const int d = l % sd.n_bins;
+    float g[kWin], n0[kWin];
+    energy_sums<false, false, false, PB>(sd, p[l], p[L + l], p[2 * L + l], g, nullptr, nullptr, 0.0f, d);
+    ray_n0<PB>(sd, d, n0);
 #pragma unroll
     for (int w = 0; w < kWin; ++w) {
-      const double ch = (double)sd.n0[w] * (double)g[w];
+      const double ch = (double)n0[w] * (double)g[w];
       const double cv = (double)c[w * L + l];
       term += ch - cv - (cv > 0.0 ? cv * log(ch / cv) : 0.0);
     }
@@ -187,17 +192,28 @@ static inline dim3 pix_grid(const ScanDesc &sd) {
 
 hipError_t launch_spectral_model(const ScanDesc &sd, const float *p, const float *c, float *chat, float *r,
                                  float *G, float *H, float *Hp, bool fp64, hipStream_t st) {
-  if (fp64)
-    hipLaunchKernelGGL(k_spectral_model<double>, ray_grid(sd), dim3(256), 0, st, sd, p, c, chat, r, G, H, Hp);
-  else
-    hipLaunchKernelGGL(k_spectral_model<float>, ray_grid(sd), dim3(256), 0, st, sd, p, c, chat, r, G, H, Hp);
+#define OSSCIR_MODEL(T, PB) \
+  hipLaunchKernelGGL((k_spectral_model<T, PB>), ray_grid(sd), dim3(256), 0, st, sd, p, c, chat, r, G, H, Hp)
+  if (sd.per_bin) {
+    if (fp64) OSSCIR_MODEL(double, true); else OSSCIR_MODEL(float, true);
+  } else {
+    if (fp64) OSSCIR_MODEL(double, false); else OSSCIR_MODEL(float, false);
+  }
+#undef OSSCIR_MODEL
   return hipGetLastError();
 }
 
 hipError_t launch_spectral_dual(const ScanDesc &sd, const float *p, const float *c, float *y, float *qS,
                                 float lambda, bool clip, bool block, bool fp64, hipStream_t st) {
-#define OSSCIR_DUAL(T, C, B) \
-  hipLaunchKernelGGL((k_spectral_dual<T, C, B>), ray_grid(sd), dim3(256), 0, st, sd, p, c, y, qS, lambda)
+#define OSSCIR_DUAL(T, C, B)                                                                                \
+  do {                                                                                                      \
+    if (sd.per_bin)                                                                                         \
+      hipLaunchKernelGGL((k_spectral_dual<T, C, B, true>), ray_grid(sd), dim3(256), 0, st, sd, p, c, y, qS,  \
+                         lambda);                                                                           \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_spectral_dual<T, C, B, false>), ray_grid(sd), dim3(256), 0, st, sd, p, c, y, qS, \
+                         lambda);                                                                           \
+  } while (0)
   if (fp64) {
     if (clip) {
       if (block) OSSCIR_DUAL(double, true, true); else OSSCIR_DUAL(double, true, false);
@@ -259,7 +275,10 @@ hipError_t launch_dtpl(const ScanDesc &sd, const float *f, const float *c, float
                        double *partial, double *out, hipStream_t st) {
   hipError_t e = launch_forward(sd, f, 3, p_scratch, pack, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dtpl_partial, ray_grid(sd), dim3(256), 0, st, sd, p_scratch, c, partial);
+  if (sd.per_bin)
+    hipLaunchKernelGGL(k_dtpl_partial<true>, ray_grid(sd), dim3(256), 0, st, sd, p_scratch, c, partial);
+  else
+    hipLaunchKernelGGL(k_dtpl_partial<false>, ray_grid(sd), dim3(256), 0, st, sd, p_scratch, c, partial);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, dtpl_partial_count(sd), out);

@@ -23,9 +23,12 @@ __device__ __forceinline__ constexpr int ut(int m, int n) { return m == 0 ? n : 
 // a ray whose every z_i >= zshift > 0 (all energies on the exponential
 // branch).  The ratios a_w / g_w and Hb_w / g_w are unchanged; g_w carries
 // the factor exp(zshift).
-template <bool NEED_A, bool NEED_HB, bool SHIFT = false>
+// PB: the window responses are those of detector bin d (one float4 per
+// energy), the products with mu formed here instead of read from the table.
+template <bool NEED_A, bool NEED_HB, bool SHIFT = false, bool PB = false>
 __device__ __forceinline__ void energy_sums(const ScanDesc &sd, float p0, float p1, float p2, float g[kWin],
-                                            float a[kWin * kMat], float hb[kWin * 6], float zshift = 0.0f) {
+                                            float a[kWin * kMat], float hb[kWin * 6], float zshift = 0.0f,
+                                            int d = 0) {
 #pragma unroll
   for (int w = 0; w < kWin; ++w) g[w] = 0.0f;
   if (NEED_A) {
@@ -37,6 +40,7 @@ __device__ __forceinline__ void energy_sums(const ScanDesc &sd, float p0, float 
     for (int j = 0; j < kWin * 6; ++j) hb[j] = 0.0f;
   }
   const OSSCIR_CONST float *tab = as_const(sd.tab);
+  const float4 *__restrict__ sb = PB ? sd.sbin + d : nullptr;
   for (int i = 0; i < sd.n_energy; ++i) {
     const OSSCIR_CONST float *t = tab + i * kTab;
     float E, E1, E2;
@@ -47,15 +51,38 @@ __device__ __forceinline__ void energy_sums(const ScanDesc &sd, float p0, float 
       const float z = __fmaf_rn(t[kTabMu + 2], p2, __fmaf_rn(t[kTabMu + 1], p1, t[kTabMu] * p0));
       softexp3(z, E, E1, E2);
     }
+    if (PB) {
+      const float4 s4 = sb[(size_t)i * sd.n_bins];
+      const float sw[kWin] = {s4.x, s4.y, s4.z, s4.w};
 #pragma unroll
-    for (int w = 0; w < kWin; ++w) g[w] = __fmaf_rn(t[kTabS + w], E, g[w]);
-    if (NEED_A) {
+      for (int w = 0; w < kWin; ++w) g[w] = __fmaf_rn(sw[w], E, g[w]);
+      if (NEED_A) {
 #pragma unroll
-      for (int j = 0; j < kWin * kMat; ++j) a[j] = __fmaf_rn(t[kTabSMu + j], E1, a[j]);
-    }
-    if (NEED_HB) {
+        for (int w = 0; w < kWin; ++w) {
+          const float e1 = sw[w] * E1;
 #pragma unroll
-      for (int j = 0; j < kWin * 6; ++j) hb[j] = __fmaf_rn(t[kTabSMuMu + j], E2, hb[j]);
+          for (int m = 0; m < kMat; ++m) a[w * kMat + m] = __fmaf_rn(e1, t[kTabMu + m], a[w * kMat + m]);
+        }
+      }
+      if (NEED_HB) {
+#pragma unroll
+        for (int w = 0; w < kWin; ++w) {
+          const float e2 = sw[w] * E2;
+#pragma unroll
+          for (int j = 0; j < 6; ++j) hb[w * 6 + j] = __fmaf_rn(e2, t[kTabMuMu + j], hb[w * 6 + j]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int w = 0; w < kWin; ++w) g[w] = __fmaf_rn(t[kTabS + w], E, g[w]);
+      if (NEED_A) {
+#pragma unroll
+        for (int j = 0; j < kWin * kMat; ++j) a[j] = __fmaf_rn(t[kTabSMu + j], E1, a[j]);
+      }
+      if (NEED_HB) {
+#pragma unroll
+        for (int j = 0; j < kWin * 6; ++j) hb[j] = __fmaf_rn(t[kTabSMuMu + j], E2, hb[j]);
+      }
     }
   }
 }
@@ -64,10 +91,10 @@ __device__ __forceinline__ void energy_sums(const ScanDesc &sd, float p0, float 
 // if a window sum underflows (an iterate far outside the physical range),
 // the sums are recomputed with the exponent shifted by min_i z_i.  Returns
 // the factor (<= 1) that turns the returned g_w into the true sums.
-template <bool NEED_A, bool NEED_HB>
+template <bool NEED_A, bool NEED_HB, bool PB = false>
 __device__ __forceinline__ float energy_sums_safe(const ScanDesc &sd, float p0, float p1, float p2, float g[kWin],
-                                                  float a[kWin * kMat], float hb[kWin * 6]) {
-  energy_sums<NEED_A, NEED_HB>(sd, p0, p1, p2, g, a, hb);
+                                                  float a[kWin * kMat], float hb[kWin * 6], int d = 0) {
+  energy_sums<NEED_A, NEED_HB, false, PB>(sd, p0, p1, p2, g, a, hb, 0.0f, d);
   const float gmin = fminf(fminf(g[0], g[1]), fminf(g[2], g[3]));
   if (gmin >= 1e-30f) return 1.0f;
   float zmin = 3.0e38f;
@@ -76,8 +103,23 @@ __device__ __forceinline__ float energy_sums_safe(const ScanDesc &sd, float p0, 
     zmin = fminf(zmin, __fmaf_rn(t[kTabMu + 2], p2, __fmaf_rn(t[kTabMu + 1], p1, t[kTabMu] * p0)));
   }
   if (!(zmin > 0.0f)) return 1.0f;  // some energy on the linear branch: no underflow possible
-  energy_sums<NEED_A, NEED_HB, true>(sd, p0, p1, p2, g, a, hb, zmin);
+  energy_sums<NEED_A, NEED_HB, true, PB>(sd, p0, p1, p2, g, a, hb, zmin, d);
   return __expf(-zmin);
+}
+
+// Incident counts of window w on the ray of detector bin d.
+template <bool PB>
+__device__ __forceinline__ void ray_n0(const ScanDesc &sd, int d, float n0[kWin]) {
+  if (PB) {
+    const float4 v = sd.n0bin[d];
+    n0[0] = v.x;
+    n0[1] = v.y;
+    n0[2] = v.z;
+    n0[3] = v.w;
+  } else {
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) n0[w] = sd.n0[w];
+  }
 }
 
 // Per-ray p-space Hessian  H = sum_w c_w a_w a_w^T - sum_w (r_w / g_w) Hb_w
@@ -103,7 +145,7 @@ __device__ __forceinline__ void ray_hessian(const T a[kWin][kMat], const T cw[kW
 // preconditioner terms S (block) or h (diag) for the back-projection.
 // CLIP: D = G^+T H^+ G^+ built from the column-equilibrated G and solved as
 // (I + Sigma^-1/2 D Sigma^-1/2) z = Sigma^-1/2 (r - y).
-template <typename T, bool CLIP, bool BLOCK>
+template <typename T, bool CLIP, bool BLOCK, bool PB = false>
 __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const float *__restrict__ p,
                                                   const float *__restrict__ c, float *__restrict__ y,
                                                   float *__restrict__ qS, float lambda, int l) {
@@ -117,15 +159,17 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
     for (int j = 0; j < 9; ++j) qS[j * L + l] = 0.0f;
     return;
   }
-  float g[kWin], af[kWin * kMat], hb[kWin * 6];
-  const float scale = energy_sums_safe<true, CLIP>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb);
+  const int d = l % sd.n_bins;
+  float g[kWin], af[kWin * kMat], hb[kWin * 6], n0[kWin];
+  const float scale = energy_sums_safe<true, CLIP, PB>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb, d);
+  ray_n0<PB>(sd, d, n0);
 
   T a[kWin][kMat], cw[kWin], rw[kWin], yw[kWin], sig[kWin];
 #pragma unroll
   for (int w = 0; w < kWin; ++w) {
     const float cf = c[w * L + l];
     cw[w] = (T)cf;
-    rw[w] = (T)(cf - sd.n0[w] * g[w] * scale);
+    rw[w] = (T)(cf - n0[w] * g[w] * scale);
     yw[w] = (T)y[w * L + l];
     const T ig = T(1) / (T)g[w];
 #pragma unroll

@@ -32,7 +32,7 @@ class _Geometry(ctypes.Structure):
 
 class _Spectral(ctypes.Structure):
     _fields_ = [("n_mat", c_int32), ("n_win", c_int32), ("n_energy", c_int32),
-                ("mu", _dp), ("s", _dp), ("n0", _dp)]
+                ("mu", _dp), ("s", _dp), ("n0", _dp), ("n_resp", c_int32)]
 
 
 class _Params(ctypes.Structure):
@@ -174,8 +174,12 @@ class Plan:
         self._mu = np.ascontiguousarray(spec.mu, dtype=np.float64)
         self._s = np.ascontiguousarray(spec.s, dtype=np.float64)
         self._n0 = np.ascontiguousarray(spec.n0, dtype=np.float64)
-        sp = _Spectral(self._mu.shape[0], self._s.shape[0], self._s.shape[1],
-                       self._mu.ctypes.data_as(_dp), self._s.ctypes.data_as(_dp), self._n0.ctypes.data_as(_dp))
+        # s [W, I] shared by every ray, or [D, W, I] per detector bin
+        n_resp = self._s.shape[0] if self._s.ndim == 3 else 1
+        self.per_bin = self._s.ndim == 3
+        sp = _Spectral(self._mu.shape[0], self._s.shape[-2], self._s.shape[-1],
+                       self._mu.ctypes.data_as(_dp), self._s.ctypes.data_as(_dp), self._n0.ctypes.data_as(_dp),
+                       n_resp)
         h = c_void_p()
         _check(lib.osscir_plan_create(ctypes.byref(g), ctypes.byref(sp), ctypes.byref(h)))
         self._h = h
@@ -318,8 +322,10 @@ def mu_pc_basis(spec):
     mu = np.ascontiguousarray(spec.mu, dtype=np.float64)
     s = np.ascontiguousarray(spec.s, dtype=np.float64)
     n0 = np.ascontiguousarray(spec.n0, dtype=np.float64)
+    if s.ndim != 2:
+        raise ValueError("mu-PC needs one shared window response s [W, I]")
     sp = _Spectral(mu.shape[0], s.shape[0], s.shape[1], mu.ctypes.data_as(_dp), s.ctypes.data_as(_dp),
-                   n0.ctypes.data_as(_dp))
+                   n0.ctypes.data_as(_dp), 1)
     B = np.zeros((3, 3))
     mu_t = np.zeros_like(mu)
     _check(lib.osscir_mu_pc_basis(ctypes.byref(sp), B.ctypes.data_as(_dp), mu_t.ctypes.data_as(_dp)))

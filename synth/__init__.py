@@ -160,6 +160,81 @@ def make_spectral(e_lo: int, e_hi: int, kvp: float, i0: float,
     return Spectral(mu=attenuation_table(energies), s=s, n0=np.full(len(edges), float(i0)))
 
 
+@dataclasses.dataclass(frozen=True)
+class DetectorSpectral:
+    """Per-detector-bin window responses and incident counts (a calibrated
+    photon-counting detector): the same bin has the same response in every
+    view."""
+    mu: np.ndarray   # [M][I]
+    s: np.ndarray    # [D][W][I], each (d, w) row sums to one
+    n0: np.ndarray   # [D][W] incident photons per ray per window
+
+    @property
+    def n_mat(self) -> int:
+        return self.mu.shape[0]
+
+    @property
+    def n_bins(self) -> int:
+        return self.s.shape[0]
+
+    @property
+    def n_win(self) -> int:
+        return self.s.shape[1]
+
+    @property
+    def n_energy(self) -> int:
+        return self.s.shape[2]
+
+    def for_rays(self, n_views: int) -> "RaySpectral":
+        """The same tables per ray l = v * n_bins + d."""
+        return RaySpectral(mu=self.mu, s=np.tile(self.s, (n_views, 1, 1)), n0=np.tile(self.n0, (n_views, 1)))
+
+
+@dataclasses.dataclass(frozen=True)
+class RaySpectral:
+    """Per-ray window responses s [L][W][I] and incident counts n0 [L][W]."""
+    mu: np.ndarray
+    s: np.ndarray
+    n0: np.ndarray
+
+    @property
+    def n_mat(self) -> int:
+        return self.mu.shape[0]
+
+    @property
+    def n_win(self) -> int:
+        return self.s.shape[1]
+
+    @property
+    def n_energy(self) -> int:
+        return self.s.shape[2]
+
+
+def make_detector_spectral(n_bins: int, e_lo: int, e_hi: int, kvp: float, i0: float, seed: int,
+                           edge_jitter_kev: float = 1.5, blur_kev=(4.0, 6.0), gain_jitter: float = 0.1,
+                           edges=None, e_step: int = 1) -> DetectorSpectral:
+    """Bin-to-bin variation of a photon-counting detector: every bin's window
+    thresholds shifted by N(0, edge_jitter_kev) (kept increasing), its energy
+    blur drawn uniformly from blur_kev, and its incident counts per window
+    scaled by 1 + gain_jitter N(0, 1) (clipped to [0.5, 1.5])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    energies = np.arange(e_lo, e_hi + 1, e_step, dtype=np.float64)
+    if edges is None:
+        edges = ((20.0, 35.0), (35.0, 50.0), (50.0, 65.0), (65.0, float(kvp)))
+    thr = np.array([lo for lo, _ in edges] + [edges[-1][1]], dtype=np.float64)
+    W = len(edges)
+    s = np.empty((n_bins, W, energies.size))
+    n0 = np.empty((n_bins, W))
+    for d in range(n_bins):
+        t = thr.copy()
+        t[:-1] += rng.normal(0.0, edge_jitter_kev, W)   # the top of the last window stays at kVp
+        t = np.maximum.accumulate(t + np.arange(W + 1) * 1e-6)
+        blur = rng.uniform(blur_kev[0], blur_kev[1])
+        s[d] = spectral_response(energies, kvp, list(zip(t[:-1], t[1:])), blur)
+        n0[d] = i0 * np.clip(1.0 + gain_jitter * rng.standard_normal(W), 0.5, 1.5)
+    return DetectorSpectral(mu=attenuation_table(energies), s=s, n0=n0)
+
+
 # ----------------------------------------------------------------- phantom
 
 def disk_phantom(n: int, fov_cm: float, disks: List[Tuple[float, float, float, Tuple[float, float, float]]],

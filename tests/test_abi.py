@@ -52,3 +52,13 @@ def test_errors_are_reported_without_a_device():
     assert lib.osscir_batch_iterate(None, 1, 1, None) == -1
     assert lib.osscir_batch_clear_slot(None, 0) == -1
     assert lib.osscir_batch_get_config(None, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libosscir.so not built")
+def test_spectral_struct_layout_matches_header():
+    """The binding's osscir_spectral has the header's fields in order."""
+    from paper_1801_06263_amd import osscir
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\} osscir_spectral;", src).group(1)
+    names = re.findall(r"\*?\s*(\w+)\s*[,;]", body)
+    assert names == [n for n, _ in osscir._Spectral._fields_]

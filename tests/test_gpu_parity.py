@@ -332,3 +332,88 @@ def test_dtpl_parity(tiny):
     hist = host(plan.mocca_iterate(st, Params(3e-7), 5, dtpl=True))
     d5 = float(plan.dtpl(st.f, st.c).item())
     assert hist[-1] == d5 and np.all(np.diff(hist) < 0)
+
+
+# ---------------------------------------------------------------- per-detector-bin spectra
+
+@pytest.fixture(scope="module")
+def tiny_det():
+    """The tiny scan with a calibrated-detector model: every bin its own
+    window responses and incident counts (jittered thresholds, blur, gain)."""
+    pr = synth.problem("tiny")
+    det = synth.make_detector_spectral(pr.geom.n_bins, 20, 119, 120.0, 1e5, 77)
+    rs = det.for_rays(pr.geom.n_views)
+    X = pj.system_matrix(pr.geom)
+    c = synth.poisson_counts(model.counts_model(X @ pr.f_true.reshape(3, -1).T, rs), pr.seed)
+    return pr, det, rs, X, c, plan_for(pr.geom, det)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_detector_spectral_model_parity(tiny_det, fp64):
+    pr, det, rs, X, c, plan = tiny_det
+    assert plan.per_bin
+    rng = np.random.default_rng(16)
+    f = pr.f_true.reshape(3, -1) * (1.3 + 0.2 * rng.standard_normal((3, X.shape[1])))
+    p32 = (X @ f.T).astype(np.float32)
+    p = p32.astype(np.float64)
+    out = plan.spectral_model(dev(sino(p32, pr.geom)), dev(sino(c, pr.geom)), fp64_small=fp64)
+    A, B, g = model.matrices_AB(p, rs)
+    chat = rs.n0 * g
+    G = model.ray_jacobian_from_A(A, rs)
+    H = model.hessian_from_AB(A, B, g, c, rs)
+    Hp = omocca.clip_negative_curvature(H)
+    assert normwise(host(out["chat"]), sino(chat, pr.geom)) <= 1e-5
+    assert normwise(host(out["r"]), sino(c - chat, pr.geom)) <= 1e-5
+    Gs = np.stack([G[:, w, m] for w in range(4) for m in range(3)])
+    for j in range(12):
+        assert normwise(host(out["G"])[j].ravel(), Gs[j]) <= 1e-5
+    iu = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    Hg, Hpg = host(out["H"]).reshape(6, -1), host(out["Hplus"]).reshape(6, -1)
+    for j, (m, n) in enumerate(iu):
+        assert np.abs(Hg[j] - H[:, m, n]).max() <= 1e-4 * np.abs(H).max()
+        assert np.abs(Hpg[j] - Hp[:, m, n]).max() <= 1e-4 * np.abs(Hp).max()
+
+
+def test_detector_zero_attenuation(tiny_det):
+    pr, det, rs, X, c, plan = tiny_det
+    V, D = pr.geom.n_views, pr.geom.n_bins
+    out = plan.spectral_model(torch.zeros(3, V, D, device="cuda"), dev(np.zeros((4, V, D))))
+    np.testing.assert_allclose(host(out["chat"]), sino(rs.n0, pr.geom), rtol=2e-6)
+
+
+def test_detector_mocca_trajectory_and_dtpl(tiny_det):
+    from paper_1801_06263_amd import Params
+    pr, det, rs, X, c, plan = tiny_det
+    lam, n_it = 3e-7, 100
+    ref, _ = omocca.mocca(X, c, rs, lam, n_it, "block", "clip")
+    st = plan.new_state(dev(sino(c, pr.geom)))
+    plan.mocca_iterate(st, Params(lam, "block", "clip", True), n_it)
+    f = host(st.f).reshape(3, -1)
+    for m in range(3):
+        rel = np.linalg.norm(f[m] - ref.f[m]) / np.linalg.norm(ref.f[m])
+        print(f"detector spectra material {m}: rel L2 {rel:.2e}")
+        assert rel <= 1e-3
+    d = float(plan.dtpl(dev(f.reshape(3, pr.geom.n, pr.geom.n)), st.c).item())
+    d_ref = model.image_objective(X, f.astype(np.float32).astype(np.float64), c, rs)
+    assert abs(d - d_ref) <= 1e-4 * abs(d_ref)
+
+
+def test_detector_spectra_in_a_batch(tiny_det):
+    """A per-bin slot beside a shared-spectrum slot in one batch: each equals
+    its single-scan run bit for bit."""
+    from paper_1801_06263_amd import Batch, Params
+    pr, det, rs, X, c, plan = tiny_det
+    plan_s = plan_for(pr.geom, pr.spec)
+    c_s = dev(sino(synth.poisson_counts(model.counts_model(X @ pr.f_true.reshape(3, -1).T, pr.spec), pr.seed),
+                   pr.geom))
+    c_d = dev(sino(c, pr.geom))
+    b = Batch(Params(1.0, "block", "clip", True), 2)
+    s0, s1 = plan.new_state(c_d), plan_s.new_state(c_s)
+    b.set_slot(0, plan, s0, 3e-7)
+    b.set_slot(1, plan_s, s1, 3e-7)
+    b.iterate(6)
+    r0, r1 = plan.new_state(c_d), plan_s.new_state(c_s)
+    plan.mocca_iterate(r0, Params(3e-7, "block", "clip", True), 6)
+    plan_s.mocca_iterate(r1, Params(3e-7, "block", "clip", True), 6)
+    assert torch.equal(s0.f, r0.f) and torch.equal(s0.y, r0.y)
+    assert torch.equal(s1.f, r1.f) and torch.equal(s1.y, r1.y)

@@ -438,3 +438,83 @@ def test_claim_block_and_mupc_beat_diag(micro):
         best[name] = min(vals)
     print(best)
     assert max(best["block"], best["mupc"]) < 0.1 * best["diag"]
+
+
+# ------------------------------------------------------------ per-detector-bin spectra
+
+def detector_micro(seed=21):
+    geom, spec, f_true = micro_problem()
+    det = synth.make_detector_spectral(geom.n_bins, 20, 119, 120.0, 1e5, seed, e_step=5)
+    return geom, det, f_true
+
+
+def test_detector_spectra_generator():
+    _, det, _ = detector_micro()
+    np.testing.assert_allclose(det.s.sum(axis=2), 1.0, rtol=1e-12)
+    assert (det.s >= 0).all() and det.s.shape == (32, 4, 20)
+    assert (det.n0 >= 0.5e5).all() and (det.n0 <= 1.5e5).all()
+    # bins differ (jittered thresholds and gains)
+    assert np.abs(det.s[0] - det.s[1]).max() > 1e-3 and np.abs(det.n0[0] - det.n0[1]).max() > 0
+
+
+def test_per_ray_tables_reduce_to_shared_ones():
+    """Per-ray tables that repeat the shared ones give the shared results."""
+    geom, spec, f_true = micro_problem()
+    X = pj.system_matrix(geom)
+    L = X.shape[0]
+    rs = synth.RaySpectral(mu=spec.mu, s=np.tile(spec.s, (L, 1, 1)), n0=np.tile(spec.n0, (L, 1)))
+    rng = np.random.default_rng(3)
+    p = X @ (f_true.reshape(3, -1) * (1 + 0.1 * rng.standard_normal((3, X.shape[1])))).T
+    c = model.counts_model(p, spec) * 1.03
+    np.testing.assert_allclose(model.counts_model(p, rs), model.counts_model(p, spec), rtol=1e-13)
+    np.testing.assert_allclose(model.hessian_p(p, c, rs), model.hessian_p(p, c, spec), rtol=1e-11,
+                               atol=1e-11 * np.abs(model.hessian_p(p, c, spec)).max())
+    st_s, _ = mocca.mocca(X, c, spec, 2e-7, 5, "block", "clip")
+    st_r, _ = mocca.mocca(X, c, rs, 2e-7, 5, "block", "clip")
+    np.testing.assert_allclose(st_r.f, st_s.f, atol=1e-10 * np.abs(st_s.f).max())
+
+
+def test_per_ray_zero_attenuation_and_monochromatic():
+    geom, det, _ = detector_micro()
+    rs = det.for_rays(geom.n_views)
+    L = geom.n_views * geom.n_bins
+    chat = model.counts_model(np.zeros((L, 3)), rs)
+    np.testing.assert_allclose(chat, rs.n0, rtol=1e-15)
+    # one energy per (bin, window): Beer-Lambert with that energy's attenuation
+    rng = np.random.default_rng(4)
+    idx = rng.integers(0, det.n_energy, (geom.n_bins, 4))
+    s1 = np.zeros_like(det.s)
+    for d in range(geom.n_bins):
+        for w in range(4):
+            s1[d, w, idx[d, w]] = 1.0
+    mono = synth.DetectorSpectral(mu=det.mu, s=s1, n0=det.n0).for_rays(geom.n_views)
+    p = rng.random((L, 3)) * np.array([5.0, 1.0, 0.01])
+    ref = rs.n0 * np.exp(-np.einsum("lm,mlw->lw", p, det.mu[:, np.tile(idx, (geom.n_views, 1))]))
+    np.testing.assert_allclose(model.counts_model(p, mono), ref, rtol=1e-13)
+
+
+def test_per_ray_derivatives_by_finite_differences():
+    geom, det, _ = detector_micro()
+    rs = det.for_rays(geom.n_views)
+    rng = np.random.default_rng(12)
+    L = geom.n_views * geom.n_bins
+    sub = rng.choice(L, 20, replace=False)
+    rsub = synth.RaySpectral(mu=rs.mu, s=rs.s[sub], n0=rs.n0[sub])
+    p = 0.5 + rng.random((20, 3)) * np.array([10.0, 1.0, 0.01])
+    c = model.counts_model(p, rsub) * (1 + 0.1 * rng.standard_normal((20, 4)))
+    H = model.hessian_p(p, c, rsub)
+    gp = model.gradient_p(p, c, rsub)
+    for m in range(3):
+        h = 1e-5 * max(1.0, abs(p[:, m]).max())
+        e = np.zeros(3)
+        e[m] = h
+        fdg = np.array([(model.dtpl(c[i], model.counts_model((p + e)[i:i + 1], _row(rsub, i))[0])
+                         - model.dtpl(c[i], model.counts_model((p - e)[i:i + 1], _row(rsub, i))[0])) / (2 * h)
+                        for i in range(20)])
+        np.testing.assert_allclose(fdg, gp[:, m], rtol=1e-6, atol=1e-6 * np.abs(gp).max())
+        fd = (model.gradient_p(p + e, c, rsub) - model.gradient_p(p - e, c, rsub)) / (2 * h)
+        np.testing.assert_allclose(fd, H[:, :, m], rtol=1e-6, atol=1e-6 * np.abs(H).max())
+
+
+def _row(rs, i):
+    return synth.RaySpectral(mu=rs.mu, s=rs.s[i:i + 1], n0=rs.n0[i:i + 1])
