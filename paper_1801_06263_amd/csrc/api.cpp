@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -45,10 +46,21 @@ WorkLayout osscir::work_layout(const ScanDesc &sd) {
   const size_t L = (size_t)sd.n_rays;
   w.p = 0;
   w.qS = align256(w.p + 3 * L * sizeof(float));
-  w.partial = align256(w.qS + 9 * L * sizeof(float));
+  w.partial = align256(w.qS + 12 * L * sizeof(float));
   w.pack = align256(w.partial + (size_t)dtpl_partial_count(sd) * sizeof(double));
   w.total = align256(w.pack + pack_scratch_bytes(sd));
   return w;
+}
+
+std::vector<int> osscir::region_tile_order(int nt) {
+  std::vector<int> order;
+  order.reserve((size_t)nt * nt);
+  const int rb = (nt + 3) / 4, cb = (nt + 1) / 2;
+  for (int band = 0; band < 4; ++band)
+    for (int half = 0; half < 2; ++half)
+      for (int ty = band * rb; ty < std::min(nt, (band + 1) * rb); ++ty)
+        for (int tx = half * cb; tx < std::min(nt, (half + 1) * cb); ++tx) order.push_back(ty * nt + tx);
+  return order;
 }
 
 int osscir::check_plan(osscir_plan plan) {
@@ -70,6 +82,7 @@ void free_plan(osscir_plan p) {
   if (p->d_pack) (void)hipFree(p->d_pack);
   if (p->d_sbin) (void)hipFree(p->d_sbin);
   if (p->d_n0bin) (void)hipFree(p->d_n0bin);
+  if (p->d_tile_order) (void)hipFree(p->d_tile_order);
   delete p;
 }
 
@@ -196,6 +209,7 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
     }
   }
 
+  const std::vector<int> tiles = region_tile_order((N + kBpTile - 1) / kBpTile);
   hipError_t e;
   if ((e = hipMalloc(&p->d_rays, rays.size() * sizeof(RayLine))) != hipSuccess ||
       (e = hipMalloc(&p->d_views, views.size() * sizeof(ViewGeom))) != hipSuccess ||
@@ -203,7 +217,8 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
       (e = hipMalloc(&p->d_rho, L * sizeof(float))) != hipSuccess ||
       (e = hipMalloc(&p->d_tab, tab.size() * sizeof(float))) != hipSuccess ||
       (per_bin && (e = hipMalloc(&p->d_sbin, sbin.size() * sizeof(float4))) != hipSuccess) ||
-      (per_bin && (e = hipMalloc(&p->d_n0bin, n0bin.size() * sizeof(float4))) != hipSuccess)) {
+      (per_bin && (e = hipMalloc(&p->d_n0bin, n0bin.size() * sizeof(float4))) != hipSuccess) ||
+      (e = hipMalloc(&p->d_tile_order, tiles.size() * sizeof(int))) != hipSuccess) {
     free_plan(p);
     return fail(OSSCIR_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
@@ -214,7 +229,9 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
       (per_bin &&
        (e = hipMemcpy(p->d_sbin, sbin.data(), sbin.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess) ||
       (per_bin && (e = hipMemcpy(p->d_n0bin, n0bin.data(), n0bin.size() * sizeof(float4), hipMemcpyHostToDevice)) !=
-                      hipSuccess)) {
+                      hipSuccess) ||
+      (e = hipMemcpy(p->d_tile_order, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice)) !=
+          hipSuccess) {
     free_plan(p);
     return hip_fail(e, "copying plan tables");
   }
@@ -230,6 +247,7 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   sd.cbin = 0.5f * (float)(D - 1);
   for (int w = 0; w < kWin; ++w) sd.n0[w] = (float)spec->n0[w];
   sd.per_bin = per_bin ? 1 : 0;
+  sd.tile_order = p->d_tile_order;
   sd.sbin = p->d_sbin;
   sd.n0bin = p->d_n0bin;
   // does any 16x16 tile's shadow exceed the back-projector's staging buffer?

@@ -210,9 +210,8 @@ int flush(osscir_batch b, hipStream_t st) {
     for (int i = 0; i < sd.n_views * nfc; ++i) items[kListFp].push_back({code | i, (double)c.fp_rays * sd.n});
     const int nsc = (sd.n_rays + c.spec_rays - 1) / c.spec_rays;
     for (int i = 0; i < nsc; ++i) items[kListSpec].push_back({code | i, (double)c.spec_rays * sd.n_energy});
-    const int nt = tiles_of(sd);
     auto &bl = items[sd.bp_wide ? kListBpWide : kListBp];
-    for (int i = 0; i < nt; ++i) bl.push_back({code | i, (double)sd.n_views});
+    for (int t : region_tile_order((sd.n + kBpTile - 1) / kBpTile)) bl.push_back({code | t, (double)sd.n_views});
   }
   const bool xcd[kLists] = {c.fp_xcd != 0, c.spec_xcd != 0, c.bp_xcd != 0, c.bp_xcd != 0};
   std::vector<int> per[kLists][kX];

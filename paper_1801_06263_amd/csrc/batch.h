@@ -19,7 +19,7 @@ struct SlotDesc {
   ScanDesc sd;
   float *f, *fbar, *y;
   const float *c;
-  float *p, *qS;          // [3][L], [9][L]
+  float *p, *qS;          // [3][L], [L][12]
   float4 *pk_xy, *pk_yx;  // packed fbar (zero border of kPad)
   float lambda;
   int first_tile;         // the slot's first entry in the per-tile partial sums

@@ -98,10 +98,12 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
       iv0s[k] = iv0;
       ives[k] = ive;
       if (!COUNT) {
-        const float4 *__restrict__ line = img + (size_t)(uu + kPad) * np + kPad;
-        fv[k][0] = line[iv0];
-        fv[k][1] = line[iv0 + 1];
-        if (THIRD) fv[k][2] = line[ive];
+        // uniform row base, non-negative 32-bit byte offsets (iv0 >= -2, ive >= -3)
+        const char *__restrict__ line = reinterpret_cast<const char *>(img + (size_t)(uu + kPad) * np);
+        const unsigned o0 = (unsigned)(iv0 + kPad) * 16u;
+        fv[k][0] = *reinterpret_cast<const float4 *>(line + o0);
+        fv[k][1] = *reinterpret_cast<const float4 *>(line + o0 + 16u);
+        if (THIRD) fv[k][2] = *reinterpret_cast<const float4 *>(line + (unsigned)(ive + kPad) * 16u);
       }
       const double du = s_u - (double)uu;
       const double dv0 = s_v - (double)iv0;
@@ -118,8 +120,9 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
         w[k][2] = XMAJOR ? chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, du, dve)
                          : chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, dve, du);
       }
-      // a column index past the image reads the zero border; its weight is irrelevant
-      if (uu >= n) {
+      // a column index past the image reads the zero border (w * 0 adds +0 to
+      // the sums); only the counting pass must drop its weights
+      if (COUNT && uu >= n) {
 #pragma unroll
         for (int j = 0; j < NC; ++j) w[k][j] = 0.0f;
       }
@@ -148,19 +151,6 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
   s0 += (double)a0;
   s1 += (double)a1;
   s2 += (double)a2;
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2).  The flat workgroup index is remapped so that XCD x processes a
-// contiguous range of (view, bin-chunk) items: an arc of views whose rays
-// mostly share one major axis, and hence one of the two packed copies.
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ bool xcd_item(int nitems, int &item) {
-  const int b = blockIdx.x;
-  const int per = (nitems + kXcds - 1) / kXcds;
-  item = (b % kXcds) * per + b / kXcds;
-  return item < nitems;
 }
 
 // One workgroup: rays (v, d0 + threadIdx.x) of one view.
@@ -200,7 +190,9 @@ __device__ __forceinline__ void forward_rays(const ScanDesc &sd, const float4 *_
       iu_hi = -1;
     }
   }
-  const int lo = wave_min(iu_lo), hi = wave_max(iu_hi);
+  // the wave's walk range is uniform: keep it (and the walk index) in SGPRs
+  const int lo = __builtin_amdgcn_readfirstlane(wave_min(iu_lo));
+  const int hi = __builtin_amdgcn_readfirstlane(wave_max(iu_hi));
   const bool any45 = __any(near45);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (active) {

@@ -53,11 +53,28 @@ struct ScanDesc {
   int per_bin;       // window responses and incident counts per detector bin
   const float4 *sbin;   // [I][D] s_{w,d,i} (w = x, y, z, w), per_bin only
   const float4 *n0bin;  // [D] incident counts per window, per_bin only
+  const int *tile_order;  // [nt * nt] back-projection tiles (ty * nt + tx) in region order
   const struct RayLine *rays;  // [L]
   const ViewGeom *views;        // [V]
   const float *rho;     // [L]
   const float *tab;     // [I][kTab]
 };
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  xcd_item remaps the flat workgroup index so that XCD x processes the
+// contiguous range x of the items: the forward projector's items are (view,
+// bin-chunk) pairs, so an XCD takes an arc of views whose rays mostly share
+// one major axis and hence one packed copy; the back-projector's items are
+// tiles in region order (ScanDesc::tile_order), so an XCD takes a compact
+// block of the image and fetches each view's bins into its L2 once.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ bool xcd_item(int nitems, int &item) {
+  const int b = blockIdx.x;
+  const int per = (nitems + kXcds - 1) / kXcds;
+  item = (b % kXcds) * per + b / kXcds;
+  return item < nitems;
+}
 
 // Pointers into the constant address space: loads through them at a
 // uniform address become scalar-cache loads into SGPRs, also after stores

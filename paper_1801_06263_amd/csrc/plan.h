@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <vector>
 
 #include "device_math.h"
 #include "kernels.h"
@@ -20,6 +21,7 @@ struct osscir_plan_s {
   float *d_tab = nullptr;
   float4 *d_sbin = nullptr;   // per-detector-bin responses [I][D]
   float4 *d_n0bin = nullptr;  // per-detector-bin incident counts [D]
+  int *d_tile_order = nullptr;  // back-projection tiles in region order
 };
 
 namespace osscir {
@@ -38,11 +40,18 @@ int check_plan(osscir_plan plan);
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Caller workspace regions: p [3][L] f32 | qS [9][L] f32 | partial sums (f64)
-// | packed images of the forward projector.
+// Caller workspace regions: p [3][L] f32 | qS [L][12] f32 (q and the step
+// terms interleaved per ray; planar scratch for the standalone step calls) |
+// partial sums (f64) | packed images of the forward projector.
 struct WorkLayout {
   size_t p = 0, qS = 0, partial = 0, pack = 0, total = 0;
 };
 WorkLayout work_layout(const ScanDesc &sd);
+
+// The 16 x 16 back-projection tiles (index ty * nt + tx) in region order:
+// the image split into 4 bands of rows x 2 halves of columns, regions one
+// after the other, row-major inside; consecutive eighths of this order are
+// compact blocks of the image (one per XCD).
+std::vector<int> region_tile_order(int nt);
 
 }  // namespace osscir

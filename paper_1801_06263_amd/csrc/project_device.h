@@ -37,9 +37,9 @@ constexpr int kBpFlush = 8;       // views summed in FP32 before the FP64 runnin
 // would fold them onto two bank groups.
 struct BinLDS {
   double2 n;   // nx, ny
-  float4 w0;   // a, hmax, kappa, q0
-  float4 w1;   // q1..q4
-  float4 w2;   // q5..q8
+  float4 w0;   // a, hmax, kappa, q8
+  float4 w1;   // q0..q3
+  float4 w2;   // q4..q7
   float4 pad;
 };
 
@@ -106,12 +106,31 @@ __device__ __forceinline__ int stage_bin_of_thread(int tid) {
   return ((tid & 63) >> 4) * 64 + (tid >> 6) * 16 + (tid & 15);
 }
 
-template <int NCH>
+// QS12: q holds 12 floats per ray (three float4: channels 0..3, 4..7, 8..11)
+// and is staged with three 16-byte loads; otherwise q is planar [c][stride].
+template <int NCH, bool QS12>
 __device__ __forceinline__ void bin_load(const RayLine *__restrict__ rays, const float *__restrict__ q,
                                          unsigned q_stride, unsigned l, BinRegs<NCH> &b) {
   b.r = rays[l];
+  if (QS12) {
+    const float4 *__restrict__ q4 = reinterpret_cast<const float4 *>(q) + 3 * (size_t)l;
+    const float4 a = q4[0];
+    b.q[0] = a.x;
+    if (NCH > 1) b.q[1] = a.y;
+    if (NCH > 2) b.q[2] = a.z;
+    if (NCH > 3) b.q[3] = a.w;
+    if (NCH > 4) {
+      const float4 c4 = q4[1];
+      b.q[4] = c4.x;
+      if (NCH > 5) b.q[5] = c4.y;
+      if (NCH > 6) b.q[6] = c4.z;
+      if (NCH > 7) b.q[7] = c4.w;
+    }
+    if (NCH > 8) b.q[8] = q4[2].x;
+  } else {
 #pragma unroll
-  for (int c = 0; c < NCH; ++c) b.q[c] = q[c * q_stride + l];
+    for (int c = 0; c < NCH; ++c) b.q[c] = q[c * q_stride + l];
+  }
 }
 
 template <int NCH>
@@ -120,9 +139,9 @@ __device__ __forceinline__ void bin_store(const BinRegs<NCH> &b, BinLDS &e) {
 #pragma unroll
   for (int c = 0; c < 9; ++c) qq[c] = c < NCH ? b.q[c] : 0.0f;
   e.n = make_double2(b.r.nx, b.r.ny);
-  e.w0 = make_float4(b.r.a, b.r.hmax, b.r.kappa, qq[0]);
-  e.w1 = make_float4(qq[1], qq[2], qq[3], qq[4]);
-  e.w2 = make_float4(qq[5], qq[6], qq[7], qq[8]);
+  e.w0 = make_float4(b.r.a, b.r.hmax, b.r.kappa, qq[8]);
+  e.w1 = make_float4(qq[0], qq[1], qq[2], qq[3]);
+  if (NCH > 4) e.w2 = make_float4(qq[4], qq[5], qq[6], qq[7]);
 }
 
 template <int NCH>
@@ -131,15 +150,13 @@ __device__ __forceinline__ void accumulate_bin(const BinLDS &e, double dx, doubl
   const float4 w0 = e.w0;
   const float w = chord_weight(nn.x, nn.y, w0.x, w0.y, w0.z, dx, dy);
   float qv[9];
-  qv[0] = w0.w;
-  if (NCH > 1) {
-    const float4 w1 = e.w1;
-    qv[1] = w1.x; qv[2] = w1.y; qv[3] = w1.z; qv[4] = w1.w;
-  }
-  if (NCH > 5) {
+  const float4 w1 = e.w1;
+  qv[0] = w1.x; qv[1] = w1.y; qv[2] = w1.z; qv[3] = w1.w;
+  if (NCH > 4) {
     const float4 w2 = e.w2;
-    qv[5] = w2.x; qv[6] = w2.y; qv[7] = w2.z; qv[8] = w2.w;
+    qv[4] = w2.x; qv[5] = w2.y; qv[6] = w2.z; qv[7] = w2.w;
   }
+  qv[8] = w0.w;
 #pragma unroll
   for (int c = 0; c < NCH; ++c) part[c] = __fmaf_rn(w, qv[c], part[c]);
 }
@@ -171,7 +188,7 @@ __device__ __forceinline__ void pixel_bins(const ScanDesc &sd, const ViewGeom &v
 // WIDE: some tile shadow may exceed kBpMaxBins bins; such views are staged
 // and accumulated in chunks with extra barriers.  The plan selects the
 // variant from the geometry, so the common case carries no chunk logic.
-template <int NCH, bool WIDE>
+template <int NCH, bool WIDE, bool QS12 = false>
 __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, int tile_y, const float *__restrict__ q,
                                                 int q_stride_i, double acc[NCH], BpShared &sh) {
   static_assert(NCH >= 1 && NCH <= 9, "1..9 channels");
@@ -197,7 +214,7 @@ __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, 
       const ViewTile vt = sh.vt[0];
       if (vt.d1 - vt.d0 + 1 <= kBpMaxBins && sb <= vt.d1 - vt.d0) {
         BinRegs<NCH> b;
-        bin_load<NCH>(rays, q, q_stride, (unsigned)vc * nb + (unsigned)(vt.d0 + sb), b);
+        bin_load<NCH, QS12>(rays, q, q_stride, (unsigned)vc * nb + (unsigned)(vt.d0 + sb), b);
         bin_store<NCH>(b, sh.bins[0][sb]);
       }
     }
@@ -217,7 +234,7 @@ __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, 
         if (j + 1 < cnt) {
           const ViewTile vn = sh.vt[j + 1];
           have_next = (!WIDE || vn.d1 - vn.d0 + 1 <= kBpMaxBins) && sb <= vn.d1 - vn.d0;
-          if (have_next) bin_load<NCH>(rays, q, q_stride, (unsigned)(v + 1) * nb + (unsigned)(vn.d0 + sb), nxt);
+          if (have_next) bin_load<NCH, QS12>(rays, q, q_stride, (unsigned)(v + 1) * nb + (unsigned)(vn.d0 + sb), nxt);
         }
         const ViewGeom vg = load_uniform(sd.views + v);
         int dlo, dhi;
@@ -233,7 +250,7 @@ __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, 
             __syncthreads();
             if (sb <= c1 - c0) {
               BinRegs<NCH> b;
-              bin_load<NCH>(rays, q, q_stride, (unsigned)v * nb + (unsigned)(c0 + sb), b);
+              bin_load<NCH, QS12>(rays, q, q_stride, (unsigned)v * nb + (unsigned)(c0 + sb), b);
               bin_store<NCH>(b, sh.bins[cur][sb]);
             }
             __syncthreads();

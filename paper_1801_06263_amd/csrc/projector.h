@@ -20,6 +20,10 @@ hipError_t launch_pack(const ScanDesc &sd, const float *f, int nch, void *pack, 
 // b[c][k] = sum_l X_{l,k} q[c][l] (chunks of 9, 6, 3, 2 or 1 channels).
 hipError_t launch_back(const ScanDesc &sd, const float *q, int nch, float *b, hipStream_t st);
 
+// Workgroups of the tile-driven back-projection kernels (all tiles of the
+// image in ScanDesc::tile_order, XCD-partitioned).
+unsigned back_blocks(const ScanDesc &sd);
+
 // nnz[l] = number of pixels with a non-zero weight on ray l.
 hipError_t launch_count(const ScanDesc &sd, int *nnz, hipStream_t st);
 

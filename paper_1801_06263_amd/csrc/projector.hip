@@ -42,10 +42,15 @@ template <int NCH, bool WIDE>
 __global__ void __launch_bounds__(256) k_back(ScanDesc sd, const float *__restrict__ q, int q_stride,
                                                float *__restrict__ b, int b_stride) {
   __shared__ BpShared sh;
+  const int nt = (sd.n + kBpTile - 1) / kBpTile;
+  int item;
+  if (!xcd_item(nt * nt, item)) return;
+  const int t = as_const(sd.tile_order)[item];
+  const int tile_y = t / nt, tile_x = t - tile_y * nt;
   double acc[NCH];
-  back_accumulate<NCH, WIDE>(sd, blockIdx.x, blockIdx.y, q, q_stride, acc, sh);
-  const int ix = blockIdx.x * kBpTile + (threadIdx.x & (kBpTile - 1));
-  const int iy = blockIdx.y * kBpTile + (threadIdx.x / kBpTile);
+  back_accumulate<NCH, WIDE>(sd, tile_x, tile_y, q, q_stride, acc, sh);
+  const int ix = tile_x * kBpTile + (threadIdx.x & (kBpTile - 1));
+  const int iy = tile_y * kBpTile + (threadIdx.x / kBpTile);
   if (ix >= sd.n || iy >= sd.n) return;
   const int k = iy * sd.n + ix;
 #pragma unroll
@@ -98,10 +103,16 @@ hipError_t launch_count(const ScanDesc &sd, int *nnz, hipStream_t st) {
   return hipGetLastError();
 }
 
+// workgroups of the tile-driven kernels: every tile, rounded up to the XCD count
+unsigned back_blocks(const ScanDesc &sd) {
+  const int nt = (sd.n + kBpTile - 1) / kBpTile;
+  return (unsigned)(((nt * nt + kXcds - 1) / kXcds) * kXcds);
+}
+
 template <int NCH>
 static hipError_t launch_back_n(const ScanDesc &sd, const float *q, int q_stride, float *b, int b_stride,
                                 hipStream_t st) {
-  const dim3 grid((sd.n + kBpTile - 1) / kBpTile, (sd.n + kBpTile - 1) / kBpTile);
+  const dim3 grid(back_blocks(sd));
   if (sd.bp_wide)
     hipLaunchKernelGGL((k_back<NCH, true>), grid, dim3(kBpTile * kBpTile), 0, st, sd, q, q_stride, b, b_stride);
   else

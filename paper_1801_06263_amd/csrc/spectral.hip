@@ -121,7 +121,12 @@ template <bool BLOCK, bool WIDE>
 __global__ void __launch_bounds__(256) k_back_primal(ScanDesc sd, const float *__restrict__ qS,
                                                       float *__restrict__ f, float *__restrict__ fbar, float lambda) {
   __shared__ BpShared sh;
-  back_primal_tile<BLOCK, WIDE, false>(sd, qS, f, fbar, lambda, blockIdx.x, blockIdx.y, sh, PrimalEpilogue{});
+  const int nt = (sd.n + kBpTile - 1) / kBpTile;
+  int item;
+  if (!xcd_item(nt * nt, item)) return;
+  const int t = as_const(sd.tile_order)[item];
+  const int tile_y = t / nt;
+  back_primal_tile<BLOCK, WIDE, false>(sd, qS, f, fbar, lambda, t - tile_y * nt, tile_y, sh, PrimalEpilogue{});
 }
 
 // ---------------------------------------------------------------- D_TPL
@@ -186,9 +191,7 @@ __global__ void __launch_bounds__(256) k_material_transform(double m00, double m
 // ---------------------------------------------------------------- launchers
 
 static inline dim3 ray_grid(const ScanDesc &sd) { return dim3((sd.n_rays + 255) / 256); }
-static inline dim3 pix_grid(const ScanDesc &sd) {
-  return dim3((sd.n + kBpTile - 1) / kBpTile, (sd.n + kBpTile - 1) / kBpTile);
-}
+static inline dim3 pix_grid(const ScanDesc &sd) { return dim3(back_blocks(sd)); }
 
 hipError_t launch_spectral_model(const ScanDesc &sd, const float *p, const float *c, float *chat, float *r,
                                  float *G, float *H, float *Hp, bool fp64, hipStream_t st) {

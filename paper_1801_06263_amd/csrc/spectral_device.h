@@ -152,11 +152,14 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
   const int L = sd.n_rays;
   if (l >= L) return;
   const float rho = sd.rho[l];
+  float4 *__restrict__ qs4 = reinterpret_cast<float4 *>(qS) + 3 * (size_t)l;
   if (!(rho > 0.0f)) {
 #pragma unroll
     for (int w = 0; w < kWin; ++w) y[w * L + l] = 0.0f;
-#pragma unroll
-    for (int j = 0; j < 9; ++j) qS[j * L + l] = 0.0f;
+    const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    qs4[0] = z4;
+    qs4[1] = z4;
+    qs4[2] = z4;
     return;
   }
   const int d = l % sd.n_bins;
@@ -266,21 +269,19 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
 #pragma unroll
     for (int w = 0; w < kWin; ++w) yw[w] = yw[w] + ss[w] * z[w];
   }
-  // outputs: y, q = G^T y, and S (block) or h (diag)
+  // outputs: y, q = G^T y, and S (block) or h (diag), the latter two
+  // interleaved per ray as 12 floats (q0..2, S0..5 or h0..2, zero padding)
 #pragma unroll
   for (int w = 0; w < kWin; ++w) y[w * L + l] = (float)yw[w];
+  float o[12];
 #pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    const T qm = a[0][m] * yw[0] + a[1][m] * yw[1] + a[2][m] * yw[2] + a[3][m] * yw[3];
-    qS[m * L + l] = (float)qm;
-  }
-  if (BLOCK) {
+  for (int m = 0; m < 3; ++m)
+    o[m] = (float)(a[0][m] * yw[0] + a[1][m] * yw[1] + a[2][m] * yw[2] + a[3][m] * yw[3]);
 #pragma unroll
-    for (int j = 0; j < 6; ++j) qS[(3 + j) * L + l] = (float)extra[j];
-  } else {
-#pragma unroll
-    for (int j = 0; j < 3; ++j) qS[(3 + j) * L + l] = (float)extra[j];
-  }
+  for (int j = 0; j < 9; ++j) o[3 + j] = (BLOCK ? j < 6 : j < 3) ? (float)extra[j < 6 ? j : 0] : 0.0f;
+  qs4[0] = make_float4(o[0], o[1], o[2], o[3]);
+  qs4[1] = make_float4(o[4], o[5], o[6], o[7]);
+  qs4[2] = make_float4(o[8], o[9], o[10], o[11]);
 }
 
 // ---------------------------------------------------------------- primal
@@ -307,7 +308,7 @@ __device__ __forceinline__ void back_primal_tile(const ScanDesc &sd, const float
                                                  int tile_x, int tile_y, BpShared &sh, const PrimalEpilogue &epi) {
   constexpr int NCH = BLOCK ? 9 : 6;
   double acc[NCH];
-  back_accumulate<NCH, WIDE>(sd, tile_x, tile_y, qS, sd.n_rays, acc, sh);
+  back_accumulate<NCH, WIDE, true>(sd, tile_x, tile_y, qS, 0, acc, sh);
   const int tx = threadIdx.x & (kBpTile - 1), ty = threadIdx.x / kBpTile;
   const int ix = tile_x * kBpTile + tx;
   const int iy = tile_y * kBpTile + ty;
