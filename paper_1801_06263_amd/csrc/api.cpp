@@ -250,7 +250,8 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   sd.tile_order = p->d_tile_order;
   sd.sbin = p->d_sbin;
   sd.n0bin = p->d_n0bin;
-  // does any 16x16 tile's shadow exceed the back-projector's staging buffer?
+  // does any 16x16 tile's shadow exceed a staging slot of the back-projector's
+  // grouped path?
   // (the same corner projection the kernel uses, in FP64 with a margin)
   sd.bp_wide = 0;
   {
@@ -268,7 +269,7 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
             hi = std::max(hi, t);
           }
           const double span = (hi - lo) * (g.sdd_cm / g.bin_cm) + 3.0;
-          if (span > kBpMaxBins - 2) {
+          if (span > kBpSlot - 2) {
             sd.bp_wide = 1;
             break;
           }

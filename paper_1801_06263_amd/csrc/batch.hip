@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) kb_spectral_dual(const SlotDesc *__restri
 }
 
 template <bool BLOCK, bool WIDE>
-__global__ void __launch_bounds__(256) kb_back_primal(const SlotDesc *__restrict__ slots,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) kb_back_primal(const SlotDesc *__restrict__ slots,
                                                        const SlotStatus *__restrict__ status, WorkList wl,
                                                        double2 *__restrict__ partial) {
   __shared__ BpShared sh;

@@ -6,12 +6,25 @@
 // views in order.  For a chunk of views at a time, one thread per view
 // projects the tile's four corners onto the detector: every ray that meets
 // the tile has its bin inside that shadow (+0.05 bin), and the same corners
-// bound the half-width of every pixel's own shadow in that view.  The bins of
-// a view (line parameters and the NCH input values) are staged in LDS by all
-// four waves; the loads of view v+1 are issued before view v is processed and
-// stored after, so each view costs one barrier.  Each thread then projects its pixel centre
-// (one reciprocal), takes the bins within the bounded half-width (+0.02 bin)
-// and accumulates w * q.
+// bound the half-width hw of every pixel's own shadow in that view.
+//
+// Common path: views are staged in groups of four, wave w staging the bins
+// of the group's view w into LDS (line parameters and the NCH input values,
+// one bin per lane, up to 64); slots past a view's shadow hold a null record
+// whose weight is exactly 0.  The loads of the next group are issued before
+// the current group is processed and stored after it, so a group costs two
+// barriers.  A pixel's non-zero weights in a view lie on the bins inside
+// [tau - hw, tau + hw], tau being its centre's detector position: at most
+// K = floor(2 hw) + 1 consecutive bins.  Every thread reads, in each of the
+// group's views, a window of Kmax = max K of the group staged bins starting
+// at ceil(tau - hw), clamped into the staged range; the bins of a window
+// outside the pixel's shadow have weight exactly 0.  Kmax is uniform over the
+// workgroup, so the loop carries no per-lane bounds or divergence, and the
+// four views' windows are independent work within a step.
+//
+// Wide path (some tile shadow exceeds 62 bins; chosen by the plan): one view
+// at a time, up to 128 bins staged by all four waves, each thread looping
+// over its own shadow, views whose shadow exceeds 128 bins in chunks.
 //
 // The weights are chord_weight() of the same inputs as the forward
 // projector, so the result is X^T q with X's exact weights.  Products are
@@ -31,6 +44,8 @@ constexpr int kBpThreads = kBpTile * kBpTile;
 constexpr int kBpMaxBins = 128;   // bins staged per view; wider shadows take a chunked path
 constexpr int kBpViewChunk = kBpThreads;
 constexpr int kBpFlush = 8;       // views summed in FP32 before the FP64 running sum
+constexpr int kBpGroup = 4;       // views staged together (one wave each) in the common path
+constexpr int kBpSlot = 64;       // staged bins per view of a group (one lane each)
 
 // One staged bin.  The 80-byte stride (20 banks) puts the 16-byte pieces of
 // eight consecutive bins on 32 distinct LDS banks; a power-of-two stride
@@ -46,12 +61,16 @@ struct BinLDS {
 struct ViewTile {
   int d0, d1;    // bins whose rays can meet the tile
   float hw;      // bound on a pixel's shadow half-width (bins), incl. margin; < 0: use [d0, d1]
-  float pad;
+  float off;     // cbin - hw - d0: a pixel's window starts at ceil(bin_scale t + off) (staged index)
+  int nst;       // staged bins, max(0, d1 - d0 + 1)
+  int K;         // window length, min(nst, floor(2 hw) + 1); nst when hw < 0
+  int pad0, pad1;
 };
 
 struct BpShared {
   union {
-    BinLDS bins[2][kBpMaxBins];
+    BinLDS bins[2][kBpMaxBins];          // per-view staging (wide shadows)
+    BinLDS gbins[kBpGroup][kBpSlot];     // grouped staging (common path)
     float4 tile[kBpTile][kBpTile + 1];  // epilogues, after the last view
   };
   ViewTile vt[kBpViewChunk];
@@ -83,12 +102,17 @@ __device__ __forceinline__ void tile_view_bounds(const ScanDesc &sd, const ViewG
   // so bounded by the tile's extreme t; den >= dmin at every pixel centre; the
   // exact corner offsets exceed the linearised ones by at most a factor
   // 1 + 1.5 / den (a corner moves den by <= 0.71).
+  out.nst = max(0, out.d1 - out.d0 + 1);
   if (dmin > 4.0f) {
     const float A = fmaxf(fabsf(-vg.sb + vg.cb * tmin), fabsf(-vg.sb + vg.cb * tmax));
     const float B = fmaxf(fabsf(vg.cb + vg.sb * tmin), fabsf(vg.cb + vg.sb * tmax));
     out.hw = 0.5f * (A + B) / dmin * (1.0f + 1.5f / dmin) * sd.bin_scale + 0.02f;
+    out.off = sd.cbin - out.hw - (float)out.d0;
+    out.K = min(out.nst, (int)floorf(2.0f * out.hw) + 1);
   } else {
     out.hw = -1.0f;
+    out.off = 0.0f;
+    out.K = out.nst;
   }
 }
 
@@ -144,6 +168,15 @@ __device__ __forceinline__ void bin_store(const BinRegs<NCH> &b, BinLDS &e) {
   if (NCH > 4) e.w2 = make_float4(qq[4], qq[5], qq[6], qq[7]);
 }
 
+// copy of the fields of a staged bin that NCH channels use
+template <int NCH>
+__device__ __forceinline__ void load_bin(const BinLDS &src, BinLDS &e) {
+  e.n = src.n;
+  e.w0 = src.w0;
+  e.w1 = src.w1;
+  if (NCH > 4) e.w2 = src.w2;
+}
+
 template <int NCH>
 __device__ __forceinline__ void accumulate_bin(const BinLDS &e, double dx, double dy, float part[NCH]) {
   const double2 nn = e.n;
@@ -185,12 +218,12 @@ __device__ __forceinline__ void pixel_bins(const ScanDesc &sd, const ViewGeom &v
   }
 }
 
-// WIDE: some tile shadow may exceed kBpMaxBins bins; such views are staged
-// and accumulated in chunks with extra barriers.  The plan selects the
-// variant from the geometry, so the common case carries no chunk logic.
-template <int NCH, bool WIDE, bool QS12 = false>
-__device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, int tile_y, const float *__restrict__ q,
-                                                int q_stride_i, double acc[NCH], BpShared &sh) {
+// Wide path: one view per barrier; views whose shadow exceeds kBpMaxBins bins
+// are staged and accumulated in chunks with extra barriers.
+template <int NCH, bool QS12>
+__device__ __forceinline__ void back_accumulate_views(const ScanDesc &sd, int tile_x, int tile_y,
+                                                      const float *__restrict__ q, int q_stride_i, double acc[NCH],
+                                                      BpShared &sh) {
   static_assert(NCH >= 1 && NCH <= 9, "1..9 channels");
   const int tid = threadIdx.x;
   const int ix = tile_x * kBpTile + (tid & (kBpTile - 1));
@@ -212,7 +245,7 @@ __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, 
     __syncthreads();
     {
       const ViewTile vt = sh.vt[0];
-      if (vt.d1 - vt.d0 + 1 <= kBpMaxBins && sb <= vt.d1 - vt.d0) {
+      if (sb < vt.nst && vt.nst <= kBpMaxBins) {
         BinRegs<NCH> b;
         bin_load<NCH, QS12>(rays, q, q_stride, (unsigned)vc * nb + (unsigned)(vt.d0 + sb), b);
         bin_store<NCH>(b, sh.bins[0][sb]);
@@ -233,18 +266,19 @@ __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, 
         bool have_next = false;
         if (j + 1 < cnt) {
           const ViewTile vn = sh.vt[j + 1];
-          have_next = (!WIDE || vn.d1 - vn.d0 + 1 <= kBpMaxBins) && sb <= vn.d1 - vn.d0;
+          have_next = sb < vn.nst && vn.nst <= kBpMaxBins;
           if (have_next) bin_load<NCH, QS12>(rays, q, q_stride, (unsigned)(v + 1) * nb + (unsigned)(vn.d0 + sb), nxt);
         }
         const ViewGeom vg = load_uniform(sd.views + v);
-        int dlo, dhi;
-        pixel_bins(sd, vg, vt, X, Y, dlo, dhi);
         const double dx = vg.sx - fx;
         const double dy = vg.sy - fy;
-        if (!WIDE || vt.d1 - vt.d0 + 1 <= kBpMaxBins) {
-          // (the plan guarantees d1 - d0 < kBpMaxBins here; the min keeps reads in the buffer regardless)
+        if (vt.nst <= kBpMaxBins) {
+          int dlo, dhi;
+          pixel_bins(sd, vg, vt, X, Y, dlo, dhi);
           if (inside) accumulate_bins<NCH>(sh.bins[cur], dlo - vt.d0, min(dhi - vt.d0, kBpMaxBins - 1), dx, dy, part);
         } else {
+          int dlo, dhi;
+          pixel_bins(sd, vg, vt, X, Y, dlo, dhi);
           for (int c0 = vt.d0; c0 <= vt.d1; c0 += kBpMaxBins) {
             const int c1 = min(vt.d1, c0 + kBpMaxBins - 1);
             __syncthreads();
@@ -264,6 +298,124 @@ __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, 
       for (int c = 0; c < NCH; ++c) acc[c] += (double)part[c];
     }
   }
+}
+
+// Loads of the bin staged by this thread in a group: view j of the chunk
+// starting at vc (wave su of the group), bin d0 + sl.  false: a null slot.
+template <int NCH, bool QS12>
+__device__ __forceinline__ bool group_load(const RayLine *__restrict__ rays, const float *__restrict__ q,
+                                           unsigned q_stride, unsigned nb, const BpShared &sh, int vc, int j, int cnt,
+                                           int sl, BinRegs<NCH> &b) {
+  if (j >= cnt) return false;
+  const ViewTile vt = sh.vt[j];
+  if (sl >= min(vt.nst, kBpSlot)) return false;
+  bin_load<NCH, QS12>(rays, q, q_stride, (unsigned)(vc + j) * nb + (unsigned)(vt.d0 + sl), b);
+  return true;
+}
+
+template <int NCH>
+__device__ __forceinline__ void group_store(const BinRegs<NCH> &b, bool have, BinLDS &e) {
+  if (have) {
+    bin_store<NCH>(b, e);
+  } else {
+    BinRegs<NCH> z;
+    z.r = RayLine{0.0, 0.0, 0.0f, 0.0f, 0.0f, 0.0f};  // weight med3((0 - 0) * 0, 0, 0) = 0
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) z.q[c] = 0.0f;
+    bin_store<NCH>(z, e);
+  }
+}
+
+// Common path (every tile shadow within kBpSlot - 2 bins; the plan checks).
+template <int NCH, bool QS12>
+__device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int tile_x, int tile_y,
+                                                        const float *__restrict__ q, int q_stride_i, double acc[NCH],
+                                                        BpShared &sh) {
+  const int tid = threadIdx.x;
+  const int ix = tile_x * kBpTile + (tid & (kBpTile - 1));
+  const int iy = tile_y * kBpTile + (tid / kBpTile);
+  const int V = sd.n_views;
+  const unsigned nb = (unsigned)sd.n_bins, q_stride = (unsigned)q_stride_i;
+  const RayLine *__restrict__ rays = sd.rays;
+  const float X = (float)ix - sd.c0;  // centred, for the detector projection
+  const float Y = (float)iy - sd.c0;
+  const double fx = (double)ix, fy = (double)iy;
+  const int su = tid >> 6, sl = tid & 63;  // staged slot: view su of the group, bin sl
+  static_assert(kBpGroup * 64 == kBpThreads && kBpSlot == 64, "one wave per view, one lane per bin");
+  static_assert(kBpViewChunk % kBpFlush == 0 && kBpFlush % kBpGroup == 0, "flushes at group ends");
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
+  for (int vc = 0; vc < V; vc += kBpViewChunk) {
+    const int cnt = min(kBpViewChunk, V - vc);
+    __syncthreads();  // the previous chunk is done with sh
+    if (tid < cnt) tile_view_bounds(sd, sd.views[vc + tid], tile_x, tile_y, sh.vt[tid]);
+    __syncthreads();
+    BinRegs<NCH> nxt;
+    bool have = group_load<NCH, QS12>(rays, q, q_stride, nb, sh, vc, su, cnt, sl, nxt);
+    float part[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) part[c] = 0.0f;
+    for (int g0 = 0; g0 < cnt; g0 += kBpGroup) {
+      __syncthreads();  // the previous group's windows have been read
+      group_store<NCH>(nxt, have, sh.gbins[su][sl]);
+      __syncthreads();
+      have = group_load<NCH, QS12>(rays, q, q_stride, nb, sh, vc, g0 + kBpGroup + su, cnt, sl, nxt);
+      float t[kBpGroup];
+      int nst[kBpGroup], s[kBpGroup];
+      double dx[kBpGroup], dy[kBpGroup];
+      int kmax = 0;
+#pragma unroll
+      for (int u = 0; u < kBpGroup; ++u) {
+        t[u] = 0.0f;
+        nst[u] = 0;
+        dx[u] = 0.0;
+        dy[u] = 0.0;
+        const int j = g0 + u;
+        if (j < cnt) {
+          const ViewTile vt = sh.vt[j];
+          const ViewGeom vg = load_uniform(sd.views + vc + j);
+          nst[u] = min(__builtin_amdgcn_readfirstlane(vt.nst), kBpSlot);
+          kmax = max(kmax, min(__builtin_amdgcn_readfirstlane(vt.K), nst[u]));
+          const float num = __fmaf_rn(vg.cb, Y, -vg.sb * X);
+          const float den = __fmaf_rn(-vg.sb, Y, __fmaf_rn(-vg.cb, X, sd.sid_px));
+          t[u] = __fmaf_rn(num * __builtin_amdgcn_rcpf(den), sd.bin_scale, vt.off);
+          dx[u] = vg.sx - fx;
+          dy[u] = vg.sy - fy;
+        }
+      }
+      // window u: [s, s + kmax) inside [0, max(nst, kmax)) within the slot,
+      // covering the staged part of the pixel's shadow (at most K <= kmax bins)
+#pragma unroll
+      for (int u = 0; u < kBpGroup; ++u) s[u] = min(max((int)ceilf(t[u]), 0), max(0, nst[u] - kmax));
+      for (int i = 0; i < kmax; ++i) {
+#pragma unroll
+        for (int u = 0; u < kBpGroup; u += 2) {
+          BinLDS e0, e1;  // two views' reads in flight before the first weight
+          load_bin<NCH>(sh.gbins[u][s[u] + i], e0);
+          load_bin<NCH>(sh.gbins[u + 1][s[u + 1] + i], e1);
+          accumulate_bin<NCH>(e0, dx[u], dy[u], part);
+          accumulate_bin<NCH>(e1, dx[u + 1], dy[u + 1], part);
+        }
+      }
+      if ((g0 + kBpGroup) % kBpFlush == 0 || g0 + kBpGroup >= cnt) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          acc[c] += (double)part[c];
+          part[c] = 0.0f;
+        }
+      }
+    }
+  }
+}
+
+template <int NCH, bool WIDE, bool QS12 = false>
+__device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, int tile_y, const float *__restrict__ q,
+                                                int q_stride_i, double acc[NCH], BpShared &sh) {
+  static_assert(NCH >= 1 && NCH <= 9, "1..9 channels");
+  if (WIDE)
+    back_accumulate_views<NCH, QS12>(sd, tile_x, tile_y, q, q_stride_i, acc, sh);
+  else
+    back_accumulate_grouped<NCH, QS12>(sd, tile_x, tile_y, q, q_stride_i, acc, sh);
 }
 
 }  // namespace osscir

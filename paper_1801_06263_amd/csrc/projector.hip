@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__re
 // ----------------------------------------------------------------- back
 
 template <int NCH, bool WIDE>
-__global__ void __launch_bounds__(256) k_back(ScanDesc sd, const float *__restrict__ q, int q_stride,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_back(ScanDesc sd, const float *__restrict__ q, int q_stride,
                                                float *__restrict__ b, int b_stride) {
   __shared__ BpShared sh;
   const int nt = (sd.n + kBpTile - 1) / kBpTile;

@@ -118,7 +118,7 @@ __global__ void k_scale_steps(int count, float lambda, float *__restrict__ v) {
 // ---------------------------------------------------------------- primal
 
 template <bool BLOCK, bool WIDE>
-__global__ void __launch_bounds__(256) k_back_primal(ScanDesc sd, const float *__restrict__ qS,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_back_primal(ScanDesc sd, const float *__restrict__ qS,
                                                       float *__restrict__ f, float *__restrict__ fbar, float lambda) {
   __shared__ BpShared sh;
   const int nt = (sd.n + kBpTile - 1) / kBpTile;
