@@ -44,7 +44,7 @@ __device__ __forceinline__ void pack_block(const float *__restrict__ f, int n, i
 
 // ----------------------------------------------------------------- forward
 //
-// One thread per ray, a workgroup = 256 consecutive detector bins of one view
+// One thread per ray, a workgroup = a chunk of consecutive detector bins of one view
 // (coalesced sinogram writes).  A ray walks its major axis (the image axis
 // closer to its direction); in each column (row) the line spans less than one
 // pixel of the minor axis, so the two pixels floor(y*) and floor(y*)+1 around

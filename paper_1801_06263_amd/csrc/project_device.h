@@ -406,6 +406,7 @@ __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int 
       }
     }
   }
+  __syncthreads();  // every wave is done with the staging slots, which epilogues reuse
 }
 
 template <int NCH, bool WIDE, bool QS12 = false>

@@ -59,8 +59,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
 
 // ----------------------------------------------------------------- launchers
 
+// Rays per forward-projection workgroup (a chunk of consecutive bins of one
+// view); two waves per workgroup measured faster than one or four.
+constexpr int kFpBlock = 128;
+
 static unsigned forward_blocks(const ScanDesc &sd) {
-  const int items = sd.n_views * ((sd.n_bins + 255) / 256);
+  const int items = sd.n_views * ((sd.n_bins + kFpBlock - 1) / kFpBlock);
   return (unsigned)(((items + kXcds - 1) / kXcds) * kXcds);
 }
 
@@ -81,7 +85,7 @@ hipError_t launch_forward(const ScanDesc &sd, const float *f, int nch, float *p,
     hipLaunchKernelGGL(k_pack, pgrid, dim3(256), 0, st, f + c0 * fs, sd.n, k, pk_xy, pk_yx);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_forward<false>, fgrid, dim3(256), 0, st, sd, pk_xy, pk_yx, p + c0 * ps, (int)ps, k);
+    hipLaunchKernelGGL(k_forward<false>, fgrid, dim3(kFpBlock), 0, st, sd, pk_xy, pk_yx, p + c0 * ps, (int)ps, k);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -98,7 +102,7 @@ hipError_t launch_pack(const ScanDesc &sd, const float *f, int nch, void *pack, 
 
 hipError_t launch_count(const ScanDesc &sd, int *nnz, hipStream_t st) {
   const dim3 fgrid(forward_blocks(sd));
-  hipLaunchKernelGGL(k_forward<true>, fgrid, dim3(256), 0, st, sd, nullptr, nullptr, reinterpret_cast<float *>(nnz),
+  hipLaunchKernelGGL(k_forward<true>, fgrid, dim3(kFpBlock), 0, st, sd, nullptr, nullptr, reinterpret_cast<float *>(nnz),
                      0, 1);
   return hipGetLastError();
 }

@@ -355,7 +355,7 @@ __device__ __forceinline__ void back_primal_tile(const ScanDesc &sd, const float
     d2 += __shfl_xor(d2, o, 64);
     n2 += __shfl_xor(n2, o, 64);
   }
-  sh.tile[ty][tx] = v4;  // the last view's barrier has released the staging buffer
+  sh.tile[ty][tx] = v4;  // the gather's closing barrier has released the staging slots
   if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = make_double2(d2, n2);
   __syncthreads();
   {
