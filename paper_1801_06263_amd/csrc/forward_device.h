@@ -57,8 +57,8 @@ __device__ __forceinline__ void pack_block(const float *__restrict__ f, int n, i
 // every load issued before the weights are formed.
 //
 // The FP64 offsets from the source are formed exactly as the back-projector
-// forms them: s - (double)i for integer i is exact, so the offset of the
-// second candidate, (s - iv0) - 1, equals s - (iv0 + 1) bit for bit.
+// forms them, one rounded subtraction s - (double)i per pixel index i, so
+// every weight is bit-identical to the back-projector's.
 __device__ __forceinline__ int wave_min(int x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
@@ -75,6 +75,14 @@ __device__ __forceinline__ int wave_max(int x) {
 // are processed per step; the last step may run past the image by up to
 // kFpUnroll - 1 columns, which the zero border (kPad >= kFpUnroll) absorbs.
 constexpr int kFpUnroll = 4;
+
+// floor(x) as an integer in one instruction; x is finite and in int range
+// (a NaN gives 0)
+__device__ __forceinline__ int floor_to_int(float x) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
 static_assert(kPad >= kFpUnroll, "border must cover the unrolled tail");
 template <bool XMAJOR, bool THIRD, bool COUNT>
 __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4 *__restrict__ img, double s_u,
@@ -92,9 +100,14 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
     for (int k = 0; k < kFpUnroll; ++k) {
       const int uu = u + k;
       const float ys = __fmaf_rn(slope, (float)uu, base);
-      const float fl = floorf(ys);
-      const int iv0 = min(max((int)fl, -2), n);
-      const int ive = (ys - fl < 0.5f) ? iv0 - 1 : iv0 + 2;
+      int iv0, ive = 0;
+      if (THIRD) {
+        const float fl = floorf(ys);
+        iv0 = min(max((int)fl, -2), n);
+        ive = (ys - fl < 0.5f) ? iv0 - 1 : iv0 + 2;
+      } else {
+        iv0 = floor_to_int(__builtin_amdgcn_fmed3f(ys, -2.0f, (float)n));  // in [-2, n]
+      }
       iv0s[k] = iv0;
       ives[k] = ive;
       if (!COUNT) {
@@ -106,8 +119,9 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
         if (THIRD) fv[k][2] = *reinterpret_cast<const float4 *>(line + (unsigned)(ive + kPad) * 16u);
       }
       const double du = s_u - (double)uu;
-      const double dv0 = s_v - (double)iv0;
-      const double dv1 = dv0 - 1.0;
+      const double fv0 = (double)iv0;
+      const double dv0 = s_v - fv0;
+      const double dv1 = s_v - (fv0 + 1.0);
       if (XMAJOR) {
         w[k][0] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, du, dv0);
         w[k][1] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, du, dv1);
