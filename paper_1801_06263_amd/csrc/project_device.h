@@ -116,6 +116,18 @@ __device__ __forceinline__ void tile_view_bounds(const ScanDesc &sd, const ViewG
   }
 }
 
+// Pixel (tx, ty) of the 16 x 16 tile held by thread tid: wave w takes the
+// 8 x 8 quadrant (w & 1, w >> 1) and each group of eight lanes a 4 x 2 block.
+// An LDS read serves eight lanes at a time, and staged bins 8 apart share
+// banks (80-byte stride); the bins of a 4 x 2 block stay within fewer than 8
+// of each other for all but the views that see the block magnified most,
+// where eight pixels of one row would span up to 19.
+__device__ __forceinline__ void bp_pixel_of_thread(int tid, int &tx, int &ty) {
+  const int w = tid >> 6, g = (tid >> 3) & 7, k = tid & 7;
+  tx = (w & 1) * 8 + (g & 1) * 4 + (k & 3);
+  ty = (w >> 1) * 8 + (g >> 1) * 2 + (k >> 2);
+}
+
 template <int NCH>
 struct BinRegs {
   RayLine r;
@@ -226,8 +238,10 @@ __device__ __forceinline__ void back_accumulate_views(const ScanDesc &sd, int ti
                                                       BpShared &sh) {
   static_assert(NCH >= 1 && NCH <= 9, "1..9 channels");
   const int tid = threadIdx.x;
-  const int ix = tile_x * kBpTile + (tid & (kBpTile - 1));
-  const int iy = tile_y * kBpTile + (tid / kBpTile);
+  int tx, ty;
+  bp_pixel_of_thread(tid, tx, ty);
+  const int ix = tile_x * kBpTile + tx;
+  const int iy = tile_y * kBpTile + ty;
   const int n = sd.n, V = sd.n_views;
   const unsigned nb = (unsigned)sd.n_bins, q_stride = (unsigned)q_stride_i;
   const RayLine *__restrict__ rays = sd.rays;
@@ -332,8 +346,10 @@ __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int 
                                                         const float *__restrict__ q, int q_stride_i, double acc[NCH],
                                                         BpShared &sh) {
   const int tid = threadIdx.x;
-  const int ix = tile_x * kBpTile + (tid & (kBpTile - 1));
-  const int iy = tile_y * kBpTile + (tid / kBpTile);
+  int tx, ty;
+  bp_pixel_of_thread(tid, tx, ty);
+  const int ix = tile_x * kBpTile + tx;
+  const int iy = tile_y * kBpTile + ty;
   const int V = sd.n_views;
   const unsigned nb = (unsigned)sd.n_bins, q_stride = (unsigned)q_stride_i;
   const RayLine *__restrict__ rays = sd.rays;

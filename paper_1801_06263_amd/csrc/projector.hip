@@ -49,8 +49,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
   const int tile_y = t / nt, tile_x = t - tile_y * nt;
   double acc[NCH];
   back_accumulate<NCH, WIDE>(sd, tile_x, tile_y, q, q_stride, acc, sh);
-  const int ix = tile_x * kBpTile + (threadIdx.x & (kBpTile - 1));
-  const int iy = tile_y * kBpTile + (threadIdx.x / kBpTile);
+  int tx, ty;
+  bp_pixel_of_thread(threadIdx.x, tx, ty);
+  const int ix = tile_x * kBpTile + tx;
+  const int iy = tile_y * kBpTile + ty;
   if (ix >= sd.n || iy >= sd.n) return;
   const int k = iy * sd.n + ix;
 #pragma unroll

@@ -309,7 +309,8 @@ __device__ __forceinline__ void back_primal_tile(const ScanDesc &sd, const float
   constexpr int NCH = BLOCK ? 9 : 6;
   double acc[NCH];
   back_accumulate<NCH, WIDE, true>(sd, tile_x, tile_y, qS, 0, acc, sh);
-  const int tx = threadIdx.x & (kBpTile - 1), ty = threadIdx.x / kBpTile;
+  int tx, ty;
+  bp_pixel_of_thread(threadIdx.x, tx, ty);
   const int ix = tile_x * kBpTile + tx;
   const int iy = tile_y * kBpTile + ty;
   const bool inside = ix < sd.n && iy < sd.n;
