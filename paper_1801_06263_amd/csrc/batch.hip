@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256, 6) kb_forward(const SlotDesc *__restrict_
 }
 
 template <typename T, bool CLIP, bool BLOCK>
-__global__ void __launch_bounds__(256) kb_spectral_dual(const SlotDesc *__restrict__ slots,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) kb_spectral_dual(const SlotDesc *__restrict__ slots,
                                                          const SlotStatus *__restrict__ status, WorkList wl) {
   const int x = blockIdx.x % kXcds;
   const int stride = gridDim.x / kXcds;

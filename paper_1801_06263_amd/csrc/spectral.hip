@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(256) k_spectral_model(ScanDesc sd, const float
 // ---------------------------------------------------------------- dual step
 
 template <typename T, bool CLIP, bool BLOCK, bool PB>
-__global__ void __launch_bounds__(256) k_spectral_dual(ScanDesc sd, const float *__restrict__ p,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_spectral_dual(ScanDesc sd, const float *__restrict__ p,
                                                         const float *__restrict__ c, float *__restrict__ y,
                                                         float *__restrict__ qS, float lambda) {
   spectral_dual_ray<T, CLIP, BLOCK, PB>(sd, p, c, y, qS, lambda, blockIdx.x * blockDim.x + threadIdx.x);
