@@ -83,6 +83,7 @@ void free_plan(osscir_plan p) {
   if (p->d_sbin) (void)hipFree(p->d_sbin);
   if (p->d_n0bin) (void)hipFree(p->d_n0bin);
   if (p->d_tile_order) (void)hipFree(p->d_tile_order);
+  if (p->d_zero) (void)hipFree(p->d_zero);
   delete p;
 }
 
@@ -218,7 +219,8 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
       (e = hipMalloc(&p->d_tab, tab.size() * sizeof(float))) != hipSuccess ||
       (per_bin && (e = hipMalloc(&p->d_sbin, sbin.size() * sizeof(float4))) != hipSuccess) ||
       (per_bin && (e = hipMalloc(&p->d_n0bin, n0bin.size() * sizeof(float4))) != hipSuccess) ||
-      (e = hipMalloc(&p->d_tile_order, tiles.size() * sizeof(int))) != hipSuccess) {
+      (e = hipMalloc(&p->d_tile_order, tiles.size() * sizeof(int))) != hipSuccess ||
+      (e = hipMalloc(&p->d_zero, 256)) != hipSuccess) {
     free_plan(p);
     return fail(OSSCIR_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
@@ -231,7 +233,8 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
       (per_bin && (e = hipMemcpy(p->d_n0bin, n0bin.data(), n0bin.size() * sizeof(float4), hipMemcpyHostToDevice)) !=
                       hipSuccess) ||
       (e = hipMemcpy(p->d_tile_order, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice)) !=
-          hipSuccess) {
+          hipSuccess ||
+      (e = hipMemset(p->d_zero, 0, 256)) != hipSuccess) {
     free_plan(p);
     return hip_fail(e, "copying plan tables");
   }
@@ -248,6 +251,7 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   for (int w = 0; w < kWin; ++w) sd.n0[w] = (float)spec->n0[w];
   sd.per_bin = per_bin ? 1 : 0;
   sd.tile_order = p->d_tile_order;
+  sd.zero = p->d_zero;
   sd.sbin = p->d_sbin;
   sd.n0bin = p->d_n0bin;
   // does any 16x16 tile's shadow exceed a staging slot of the back-projector's

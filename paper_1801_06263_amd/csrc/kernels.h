@@ -54,6 +54,7 @@ struct ScanDesc {
   const float4 *sbin;   // [I][D] s_{w,d,i} (w = x, y, z, w), per_bin only
   const float4 *n0bin;  // [D] incident counts per window, per_bin only
   const int *tile_order;  // [nt * nt] back-projection tiles (ty * nt + tx) in region order
+  const float4 *zero;     // 256 bytes of zeros (a null ray record and null inputs)
   const struct RayLine *rays;  // [L]
   const ViewGeom *views;        // [V]
   const float *rho;     // [L]

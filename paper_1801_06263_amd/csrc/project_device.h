@@ -315,28 +315,38 @@ __device__ __forceinline__ void back_accumulate_views(const ScanDesc &sd, int ti
 }
 
 // Loads of the bin staged by this thread in a group: view j of the chunk
-// starting at vc (wave su of the group), bin d0 + sl.  false: a null slot.
+// starting at vc (wave su of the group), bin d0 + sl.  A thread without a bin
+// (past the view's shadow, or past the chunk) loads the plan's zero record
+// instead, whose weight is exactly 0 (med3((0 - 0) * 0, 0, 0)), so every slot
+// of the group is rewritten and no branch or select on the data is needed.
 template <int NCH, bool QS12>
-__device__ __forceinline__ bool group_load(const RayLine *__restrict__ rays, const float *__restrict__ q,
-                                           unsigned q_stride, unsigned nb, const BpShared &sh, int vc, int j, int cnt,
-                                           int sl, BinRegs<NCH> &b) {
-  if (j >= cnt) return false;
-  const ViewTile vt = sh.vt[j];
-  if (sl >= min(vt.nst, kBpSlot)) return false;
-  bin_load<NCH, QS12>(rays, q, q_stride, (unsigned)(vc + j) * nb + (unsigned)(vt.d0 + sl), b);
-  return true;
-}
-
-template <int NCH>
-__device__ __forceinline__ void group_store(const BinRegs<NCH> &b, bool have, BinLDS &e) {
-  if (have) {
-    bin_store<NCH>(b, e);
+__device__ __forceinline__ void group_load(const ScanDesc &sd, const float *__restrict__ q, unsigned q_stride,
+                                           unsigned nb, const BpShared &sh, int vc, int j, int cnt, int sl,
+                                           BinRegs<NCH> &b) {
+  const ViewTile vt = sh.vt[min(j, cnt - 1)];
+  const bool has = j < cnt && sl < min(vt.nst, kBpSlot);
+  const unsigned l = (unsigned)(vc + j) * nb + (unsigned)(vt.d0 + sl);  // used only if has
+  b.r = *(has ? sd.rays + l : reinterpret_cast<const RayLine *>(sd.zero));
+  if (QS12) {
+    const float4 *__restrict__ q4 = has ? reinterpret_cast<const float4 *>(q) + 3 * (size_t)l : sd.zero;
+    const float4 a = q4[0];
+    b.q[0] = a.x;
+    if (NCH > 1) b.q[1] = a.y;
+    if (NCH > 2) b.q[2] = a.z;
+    if (NCH > 3) b.q[3] = a.w;
+    if (NCH > 4) {
+      const float4 c4 = q4[1];
+      b.q[4] = c4.x;
+      if (NCH > 5) b.q[5] = c4.y;
+      if (NCH > 6) b.q[6] = c4.z;
+      if (NCH > 7) b.q[7] = c4.w;
+    }
+    if (NCH > 8) b.q[8] = q4[2].x;
   } else {
-    BinRegs<NCH> z;
-    z.r = RayLine{0.0, 0.0, 0.0f, 0.0f, 0.0f, 0.0f};  // weight med3((0 - 0) * 0, 0, 0) = 0
+    const float *__restrict__ qp = has ? q + l : reinterpret_cast<const float *>(sd.zero);
+    const unsigned qs = has ? q_stride : 0u;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) z.q[c] = 0.0f;
-    bin_store<NCH>(z, e);
+    for (int c = 0; c < NCH; ++c) b.q[c] = qp[c * qs];
   }
 }
 
@@ -352,7 +362,6 @@ __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int 
   const int iy = tile_y * kBpTile + ty;
   const int V = sd.n_views;
   const unsigned nb = (unsigned)sd.n_bins, q_stride = (unsigned)q_stride_i;
-  const RayLine *__restrict__ rays = sd.rays;
   const float X = (float)ix - sd.c0;  // centred, for the detector projection
   const float Y = (float)iy - sd.c0;
   const double fx = (double)ix, fy = (double)iy;
@@ -367,37 +376,38 @@ __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int 
     if (tid < cnt) tile_view_bounds(sd, sd.views[vc + tid], tile_x, tile_y, sh.vt[tid]);
     __syncthreads();
     BinRegs<NCH> nxt;
-    bool have = group_load<NCH, QS12>(rays, q, q_stride, nb, sh, vc, su, cnt, sl, nxt);
+    group_load<NCH, QS12>(sd, q, q_stride, nb, sh, vc, su, cnt, sl, nxt);
     float part[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) part[c] = 0.0f;
     for (int g0 = 0; g0 < cnt; g0 += kBpGroup) {
       __syncthreads();  // the previous group's windows have been read
-      group_store<NCH>(nxt, have, sh.gbins[su][sl]);
+      bin_store<NCH>(nxt, sh.gbins[su][sl]);
       __syncthreads();
-      have = group_load<NCH, QS12>(rays, q, q_stride, nb, sh, vc, g0 + kBpGroup + su, cnt, sl, nxt);
+      group_load<NCH, QS12>(sd, q, q_stride, nb, sh, vc, g0 + kBpGroup + su, cnt, sl, nxt);
+      // the group's views: all reads first (views past the chunk repeat its
+      // last view with no staged bins: their slots hold zero records)
+      ViewTile vt[kBpGroup];
+      ViewGeom vg[kBpGroup];
+#pragma unroll
+      for (int u = 0; u < kBpGroup; ++u) {
+        const int j = min(g0 + u, cnt - 1);
+        vt[u] = sh.vt[j];
+        vg[u] = load_uniform(sd.views + vc + j);
+      }
       float t[kBpGroup];
       int nst[kBpGroup], s[kBpGroup];
       double dx[kBpGroup], dy[kBpGroup];
       int kmax = 0;
 #pragma unroll
       for (int u = 0; u < kBpGroup; ++u) {
-        t[u] = 0.0f;
-        nst[u] = 0;
-        dx[u] = 0.0;
-        dy[u] = 0.0;
-        const int j = g0 + u;
-        if (j < cnt) {
-          const ViewTile vt = sh.vt[j];
-          const ViewGeom vg = load_uniform(sd.views + vc + j);
-          nst[u] = min(__builtin_amdgcn_readfirstlane(vt.nst), kBpSlot);
-          kmax = max(kmax, min(__builtin_amdgcn_readfirstlane(vt.K), nst[u]));
-          const float num = __fmaf_rn(vg.cb, Y, -vg.sb * X);
-          const float den = __fmaf_rn(-vg.sb, Y, __fmaf_rn(-vg.cb, X, sd.sid_px));
-          t[u] = __fmaf_rn(num * __builtin_amdgcn_rcpf(den), sd.bin_scale, vt.off);
-          dx[u] = vg.sx - fx;
-          dy[u] = vg.sy - fy;
-        }
+        nst[u] = g0 + u < cnt ? min(__builtin_amdgcn_readfirstlane(vt[u].nst), kBpSlot) : 0;
+        kmax = max(kmax, min(__builtin_amdgcn_readfirstlane(vt[u].K), nst[u]));
+        const float num = __fmaf_rn(vg[u].cb, Y, -vg[u].sb * X);
+        const float den = __fmaf_rn(-vg[u].sb, Y, __fmaf_rn(-vg[u].cb, X, sd.sid_px));
+        t[u] = __fmaf_rn(num * __builtin_amdgcn_rcpf(den), sd.bin_scale, vt[u].off);
+        dx[u] = vg[u].sx - fx;
+        dy[u] = vg[u].sy - fy;
       }
       // window u: [s, s + kmax) inside [0, max(nst, kmax)) within the slot,
       // covering the staged part of the pixel's shadow (at most K <= kmax bins)
