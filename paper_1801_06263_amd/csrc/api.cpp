@@ -250,6 +250,7 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   sd.cbin = 0.5f * (float)(D - 1);
   for (int w = 0; w < kWin; ++w) sd.n0[w] = (float)spec->n0[w];
   sd.per_bin = per_bin ? 1 : 0;
+  sd.mfma = !per_bin && mfma_lds_bytes(I, 4) <= 65536 ? 1 : 0;
   sd.tile_order = p->d_tile_order;
   sd.zero = p->d_zero;
   sd.sbin = p->d_sbin;

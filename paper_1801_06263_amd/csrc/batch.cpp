@@ -91,6 +91,7 @@ struct osscir_batch_s {
   int partial_cap = 0;
   ListBuf lists[kLists];
   bool any_wide = false;
+  size_t spec_lds = 0;          // dynamic LDS of the spectral launch
   hipEvent_t staged = nullptr;  // the last upload from the staging buffers
   bool staged_pending = false;
   bool dirty = true;
@@ -98,6 +99,7 @@ struct osscir_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool graph_ok = false, graph_wide = false;
+  size_t graph_spec_lds = 0;
 };
 
 namespace {
@@ -183,6 +185,7 @@ int flush(osscir_batch b, hipStream_t st) {
   // slot table and tile offsets (slot order)
   int tiles = 0;
   bool any_wide = false;
+  size_t spec_lds = 0;
   std::vector<int> order;
   for (int s = 0; s < b->max_slots; ++s) {
     const HostSlot &hs = b->slots[s];
@@ -194,6 +197,7 @@ int flush(osscir_batch b, hipStream_t st) {
     b->h_slots[s].first_tile = tiles;
     tiles += b->h_slots[s].n_tiles;
     any_wide |= hs.plan->sd.bp_wide != 0;
+    if (hs.plan->sd.mfma) spec_lds = std::max(spec_lds, mfma_lds_bytes(hs.plan->sd.n_energy, c.spec_rays / 64));
     order.push_back(s);
   }
   // logical order: costliest scans first (the tail of each launch is cheap work)
@@ -267,6 +271,7 @@ int flush(osscir_batch b, hipStream_t st) {
   OSSCIR_HIP(hipEventRecord(b->staged, st), "batch: recording the upload");
   b->staged_pending = true;
   b->any_wide = any_wide;
+  b->spec_lds = spec_lds;
   b->dirty = false;
   return OSSCIR_OK;
 }
@@ -284,6 +289,7 @@ int launch_iteration(osscir_batch b, hipStream_t st, hipEvent_t *ev = nullptr) {
              "batch: forward projection");
   if (ev) OSSCIR_HIP(hipEventRecord(ev[1], st), "batch: event");
   OSSCIR_HIP(launch_batch_spectral_dual(b->d_slots, b->d_status, worklist(b, kListSpec, c.spec_wgs), c.spec_rays,
+                                        b->spec_lds,
                                         b->clip, b->block, b->fp64, st),
              "batch: spectral model and dual step");
   if (ev) OSSCIR_HIP(hipEventRecord(ev[2], st), "batch: event");
@@ -322,6 +328,7 @@ int capture(osscir_batch b, hipStream_t st) {
   OSSCIR_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "batch: instantiating the graph");
   b->graph_ok = true;
   b->graph_wide = b->any_wide;
+  b->graph_spec_lds = b->spec_lds;
   return OSSCIR_OK;
 }
 
@@ -433,7 +440,7 @@ int osscir_batch_iterate(osscir_batch b, int32_t n_iter, int32_t use_graph, ossc
   if ((rc = flush(b, st))) return rc;
   if (n_iter == 0) return OSSCIR_OK;
   if (use_graph) {
-    if (!b->graph_ok || b->graph_wide != b->any_wide)
+    if (!b->graph_ok || b->graph_wide != b->any_wide || b->graph_spec_lds != b->spec_lds)
       if ((rc = capture(b, st))) return rc;
     for (int i = 0; i < n_iter; ++i) OSSCIR_HIP(hipGraphLaunch(b->exec, st), "batch: graph launch");
   } else {

@@ -51,8 +51,10 @@ struct WorkList {
 
 hipError_t launch_batch_forward(const SlotDesc *slots, const SlotStatus *status, WorkList wl, int rays_per_wg,
                                 hipStream_t st);
+// lds: dynamic LDS bytes, enough for every bound slot with matrix-core energy
+// sums (mfma_lds_bytes at rays_per_wg / 64 waves), else 0
 hipError_t launch_batch_spectral_dual(const SlotDesc *slots, const SlotStatus *status, WorkList wl,
-                                      int rays_per_wg, bool clip, bool block, bool fp64, hipStream_t st);
+                                      int rays_per_wg, size_t lds, bool clip, bool block, bool fp64, hipStream_t st);
 hipError_t launch_batch_back_primal(const SlotDesc *slots, const SlotStatus *status, WorkList wl, bool block,
                                     bool wide, double2 *partial, hipStream_t st);
 hipError_t launch_batch_tick(const SlotDesc *slots, SlotStatus *status, const double2 *partial, int n_slots,

@@ -69,6 +69,7 @@ __global__ void __launch_bounds__(256, 6) kb_forward(const SlotDesc *__restrict_
 template <typename T, bool CLIP, bool BLOCK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) kb_spectral_dual(const SlotDesc *__restrict__ slots,
                                                          const SlotStatus *__restrict__ status, WorkList wl) {
+  extern __shared__ float stab[];  // matrix-core sums: the slot's table, then transposition tiles
   const int x = blockIdx.x % kXcds;
   const int stride = gridDim.x / kXcds;
   const int cnt = list_count(wl, x);
@@ -78,10 +79,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
     if (!slot_running(status, s)) continue;
     const SlotDesc sl = load_slot(slots, s);
     const int l = local * (int)blockDim.x + (int)threadIdx.x;
-    if (sl.sd.per_bin)
+    if (sl.sd.per_bin) {
       spectral_dual_ray<T, CLIP, BLOCK, true>(sl.sd, sl.p, sl.c, sl.y, sl.qS, sl.lambda, l);
-    else
+    } else if (sl.sd.mfma) {  // uniform over the workgroup, as in the single-scan kernel
+      __syncthreads();        // the previous item is done with the staged table and tiles
+      stage_table(sl.sd, stab);
+      __syncthreads();
+      spectral_dual_ray<T, CLIP, BLOCK, false, true>(sl.sd, sl.p, sl.c, sl.y, sl.qS, sl.lambda, l, stab);
+    } else {
       spectral_dual_ray<T, CLIP, BLOCK, false>(sl.sd, sl.p, sl.c, sl.y, sl.qS, sl.lambda, l);
+    }
   }
 }
 
@@ -142,9 +149,9 @@ hipError_t launch_batch_forward(const SlotDesc *slots, const SlotStatus *status,
 }
 
 hipError_t launch_batch_spectral_dual(const SlotDesc *slots, const SlotStatus *status, WorkList wl,
-                                      int rays_per_wg, bool clip, bool block, bool fp64, hipStream_t st) {
+                                      int rays_per_wg, size_t lds, bool clip, bool block, bool fp64, hipStream_t st) {
   const dim3 g((unsigned)wl.wgs), b((unsigned)rays_per_wg);
-#define OSSCIR_BDUAL(T, C, B) hipLaunchKernelGGL((kb_spectral_dual<T, C, B>), g, b, 0, st, slots, status, wl)
+#define OSSCIR_BDUAL(T, C, B) hipLaunchKernelGGL((kb_spectral_dual<T, C, B>), g, b, lds, st, slots, status, wl)
   if (fp64) {
     if (clip) {
       if (block) OSSCIR_BDUAL(double, true, true); else OSSCIR_BDUAL(double, true, false);

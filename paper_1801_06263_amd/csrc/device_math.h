@@ -188,7 +188,7 @@ __device__ __forceinline__ void spd3_inverse(const T S[6], T inv[3][3]) {
 // by Cholesky (every pivot is >= 1).
 template <typename T>
 __device__ __forceinline__ void unit_plus_psd4_solve(const T M[4][4], const T b[4], T z[4]) {
-  T L[4][4];
+  T L[4][4], il[4];  // il: reciprocal pivots
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -196,10 +196,12 @@ __device__ __forceinline__ void unit_plus_psd4_solve(const T M[4][4], const T b[
       T sum = M[i][j] + (i == j ? T(1) : T(0));
 #pragma unroll
       for (int k = 0; k < j; ++k) sum -= L[i][k] * L[j][k];
-      if (i == j)
+      if (i == j) {
         L[i][i] = sqrt(sum);
-      else
-        L[i][j] = sum / L[j][j];
+        il[i] = T(1) / L[i][i];
+      } else {
+        L[i][j] = sum * il[j];
+      }
     }
   }
   T u[4];
@@ -208,14 +210,14 @@ __device__ __forceinline__ void unit_plus_psd4_solve(const T M[4][4], const T b[
     T sum = b[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) sum -= L[i][k] * u[k];
-    u[i] = sum / L[i][i];
+    u[i] = sum * il[i];
   }
 #pragma unroll
   for (int i = 3; i >= 0; --i) {
     T sum = u[i];
 #pragma unroll
     for (int k = i + 1; k < 4; ++k) sum -= L[k][i] * z[k];
-    z[i] = sum / L[i][i];
+    z[i] = sum * il[i];
   }
 }
 

@@ -37,6 +37,22 @@ constexpr int kTabMu = 0, kTabS = 3, kTabSMu = 7, kTabSMuMu = 19;
 // neighbouring bins).
 constexpr int kTabMuMu = 7;
 
+// LDS floats per wave of the matrix-core energy sums' transposition tiles
+// (64 rays x 16 columns, +1 against bank conflicts).
+constexpr int kMfmaTileFloats = 64 * 17;
+
+// Energies of the matrix-core sums are padded with zero rows to a multiple
+// of 8 (two 4-energy steps per loop iteration).
+__host__ __device__ inline int mfma_energies(int n_energy) { return (n_energy + 7) & ~7; }
+
+// LDS bytes of a spectral kernel with the matrix-core energy sums: the
+// padded table while the sums run, then the per-wave transposition tiles.
+inline size_t mfma_lds_bytes(int n_energy, int waves) {
+  const size_t tab = (size_t)mfma_energies(n_energy) * kTab * sizeof(float);
+  const size_t tiles = (size_t)waves * kMfmaTileFloats * sizeof(float);
+  return tab > tiles ? tab : tiles;
+}
+
 // Everything a kernel needs to know about one scan.
 struct ScanDesc {
   int n;             // image side
@@ -51,6 +67,7 @@ struct ScanDesc {
   float n0[kWin];    // incident counts per window
   int bp_wide;       // some 16x16-tile shadow exceeds the back-projector's staging buffer
   int per_bin;       // window responses and incident counts per detector bin
+  int mfma;          // energy sums on the matrix cores (shared table, fits LDS)
   const float4 *sbin;   // [I][D] s_{w,d,i} (w = x, y, z, w), per_bin only
   const float4 *n0bin;  // [D] incident counts per window, per_bin only
   const int *tile_order;  // [nt * nt] back-projection tiles (ty * nt + tx) in region order

@@ -92,9 +92,8 @@ __device__ __forceinline__ void energy_sums(const ScanDesc &sd, float p0, float 
 // the sums are recomputed with the exponent shifted by min_i z_i.  Returns
 // the factor (<= 1) that turns the returned g_w into the true sums.
 template <bool NEED_A, bool NEED_HB, bool PB = false>
-__device__ __forceinline__ float energy_sums_safe(const ScanDesc &sd, float p0, float p1, float p2, float g[kWin],
-                                                  float a[kWin * kMat], float hb[kWin * 6], int d = 0) {
-  energy_sums<NEED_A, NEED_HB, false, PB>(sd, p0, p1, p2, g, a, hb, 0.0f, d);
+__device__ __forceinline__ float energy_sums_rescue(const ScanDesc &sd, float p0, float p1, float p2, float g[kWin],
+                                                    float a[kWin * kMat], float hb[kWin * 6], int d = 0) {
   const float gmin = fminf(fminf(g[0], g[1]), fminf(g[2], g[3]));
   if (gmin >= 1e-30f) return 1.0f;
   float zmin = 3.0e38f;
@@ -105,6 +104,155 @@ __device__ __forceinline__ float energy_sums_safe(const ScanDesc &sd, float p0, 
   if (!(zmin > 0.0f)) return 1.0f;  // some energy on the linear branch: no underflow possible
   energy_sums<NEED_A, NEED_HB, true, PB>(sd, p0, p1, p2, g, a, hb, zmin, d);
   return __expf(-zmin);
+}
+
+template <bool NEED_A, bool NEED_HB, bool PB = false>
+__device__ __forceinline__ float energy_sums_safe(const ScanDesc &sd, float p0, float p1, float p2, float g[kWin],
+                                                  float a[kWin * kMat], float hb[kWin * 6], int d = 0) {
+  energy_sums<NEED_A, NEED_HB, false, PB>(sd, p0, p1, p2, g, a, hb, 0.0f, d);
+  return energy_sums_rescue<NEED_A, NEED_HB, PB>(sd, p0, p1, p2, g, a, hb, d);
+}
+
+// ---------------------------------------------------------------- MFMA form
+//
+// With one response table shared by all rays, the energy sums of 64 rays
+// are a dense contraction: C[col][ray] = sum_i tab[i][col] B_col[i][ray]
+// over the table columns s_w (4), s_w mu_m (12) and s_w mu_m mu_n (24), with
+// B = softexp(-z) for the model sums, softexp'(-z) for the Jacobian rows and
+// softexp''(-z) for the curvature sums.  A wave runs it on the matrix cores
+// (v_mfma_f32_16x16x4f32: 16 table columns x 4 energies x 16 rays per
+// instruction, FP32 products and sums) while its VALU forms z and the
+// exponentials; the three column blocks are table columns 3..18 (s, s mu),
+// 19..34 and 32..47 (s mu mu).  softexp' = softexp unless z < 0: only then
+// (a wave-uniform test per 4 energies) the Jacobian rows get the correction
+// tab x (softexp' - softexp).  The results are moved to one ray per lane
+// through LDS.  Requires the whole wave (64 consecutive rays).
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+
+// All threads of the workgroup: the table into LDS in 16-byte pieces (a
+// row is 48 floats), zero rows up to mfma_energies().
+__device__ __forceinline__ void stage_table(const ScanDesc &sd, float *stab) {
+  const int n = mfma_energies(sd.n_energy) * (kTab / 4), m = sd.n_energy * (kTab / 4);
+  const float4 *__restrict__ tab = reinterpret_cast<const float4 *>(sd.tab);
+  float4 *s4 = reinterpret_cast<float4 *>(stab);
+#pragma unroll 4
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s4[i] = i < m ? tab[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// Operands of one 4-energy step of energy_sums_mfma: t = the table row of
+// this lane's energy (e0 + lane / 16); B operands softexp, softexp' -
+// softexp and softexp'' of z for the rays of the four column blocks.
+struct MfmaStep {
+  float tGA, tH1, tH2;
+  float E[4], D1[4], E2[4];
+  bool phys;
+};
+
+template <bool NEED_HB>
+__device__ __forceinline__ void mfma_operands(const float *t, int rn, const float (&pn)[4][3], MfmaStep &o) {
+  const float mu0 = t[kTabMu], mu1 = t[kTabMu + 1], mu2 = t[kTabMu + 2];
+  o.tGA = t[kTabS + rn];
+  if (NEED_HB) {
+    o.tH1 = t[kTabSMuMu + rn];
+    o.tH2 = t[kTabSMuMu + 13 + rn];
+  }
+  o.phys = true;
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const float z = __fmaf_rn(mu2, pn[nb][2], __fmaf_rn(mu1, pn[nb][1], mu0 * pn[nb][0]));
+    float e, e1, e2;
+    softexp3(z, e, e1, e2);
+    o.E[nb] = e;
+    o.D1[nb] = e1 - e;
+    o.E2[nb] = e2;
+    o.phys = o.phys && z >= 0.0f;
+  }
+}
+
+template <bool NEED_HB>
+__device__ __forceinline__ void mfma_apply(const MfmaStep &o, floatx4_t (&cGA)[4], floatx4_t (&cH1)[4],
+                                           floatx4_t (&cH2)[4]) {
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) cGA[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.tGA, o.E[nb], cGA[nb], 0, 0, 0);
+  if (NEED_HB) {
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      cH1[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.tH1, o.E2[nb], cH1[nb], 0, 0, 0);
+      cH2[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.tH2, o.E2[nb], cH2[nb], 0, 0, 0);
+    }
+  }
+}
+
+// Every thread of the workgroup calls this (it has barriers); stab holds the
+// staged table and is reused for the transposition.
+template <bool NEED_HB>
+__device__ __forceinline__ void energy_sums_mfma(const ScanDesc &sd, float *stab, float p0, float p1, float p2,
+                                                 float g[kWin], float a[kWin * kMat], float hb[kWin * 6]) {
+  const int lane = threadIdx.x & 63, rn = lane & 15, kg = lane >> 4;
+  float pn[4][3];  // the rays of the four 16-ray column blocks this lane feeds
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int src = nb * 16 + rn;
+    pn[nb][0] = __shfl(p0, src, 64);
+    pn[nb][1] = __shfl(p1, src, 64);
+    pn[nb][2] = __shfl(p2, src, 64);
+  }
+  const floatx4_t zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+  floatx4_t cGA[4], cCo[4], cH1[4], cH2[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) cGA[nb] = cCo[nb] = cH1[nb] = cH2[nb] = zero4;
+  const int ne = mfma_energies(sd.n_energy);
+  for (int e0 = 0; e0 < ne; e0 += 8) {  // two independent 4-energy steps per iteration
+    MfmaStep s0, s1;
+    mfma_operands<NEED_HB>(stab + (e0 + kg) * kTab, rn, pn, s0);
+    mfma_operands<NEED_HB>(stab + (e0 + 4 + kg) * kTab, rn, pn, s1);
+    mfma_apply<NEED_HB>(s0, cGA, cH1, cH2);
+    mfma_apply<NEED_HB>(s1, cGA, cH1, cH2);
+    if (!__all(s0.phys && s1.phys)) {
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        cCo[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(s0.tGA, s0.D1[nb], cCo[nb], 0, 0, 0);
+        cCo[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(s1.tGA, s1.D1[nb], cCo[nb], 0, 0, 0);
+      }
+    }
+  }
+  // lane holds C[4 kg + r][ray nb * 16 + rn]; move one ray's columns to its lane
+  __syncthreads();  // every wave is done with the staged table
+  float *w = stab + (threadIdx.x >> 6) * kMfmaTileFloats;
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * kg + r;
+      w[(nb * 16 + rn) * 17 + i] = cGA[nb][r] + (i >= kWin ? cCo[nb][r] : 0.0f);
+    }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < kWin; ++c) g[c] = w[lane * 17 + c];
+#pragma unroll
+  for (int c = 0; c < kWin * kMat; ++c) a[c] = w[lane * 17 + kWin + c];
+  if (NEED_HB) {
+    __syncthreads();
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) w[(nb * 16 + rn) * 17 + 4 * kg + r] = cH1[nb][r];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) hb[c] = w[lane * 17 + c];
+    __syncthreads();
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * kg + r;  // column 32 + i; the curvature sums 16..23 are columns 35..42
+        if (i >= 3 && i < 11) w[(nb * 16 + rn) * 17 + i - 3] = cH2[nb][r];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 8; ++c) hb[16 + c] = w[lane * 17 + c];
+  }
 }
 
 // Incident counts of window w on the ray of detector bin d.
@@ -145,11 +293,19 @@ __device__ __forceinline__ void ray_hessian(const T a[kWin][kMat], const T cw[kW
 // preconditioner terms S (block) or h (diag) for the back-projection.
 // CLIP: D = G^+T H^+ G^+ built from the column-equilibrated G and solved as
 // (I + Sigma^-1/2 D Sigma^-1/2) z = Sigma^-1/2 (r - y).
-template <typename T, bool CLIP, bool BLOCK, bool PB = false>
+// MFMA: the energy sums on the matrix cores (energy_sums_mfma; stab = the
+// table staged in LDS); every thread of the workgroup must call it.
+template <typename T, bool CLIP, bool BLOCK, bool PB = false, bool MFMA = false>
 __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const float *__restrict__ p,
                                                   const float *__restrict__ c, float *__restrict__ y,
-                                                  float *__restrict__ qS, float lambda, int l) {
+                                                  float *__restrict__ qS, float lambda, int l, float *stab = nullptr) {
+  static_assert(!(MFMA && PB), "the MFMA sums need one shared response table");
   const int L = sd.n_rays;
+  float g[kWin], af[kWin * kMat], hb[kWin * 6], n0[kWin];
+  if (MFMA) {
+    const bool in = l < L;
+    energy_sums_mfma<CLIP>(sd, stab, in ? p[l] : 0.0f, in ? p[L + l] : 0.0f, in ? p[2 * L + l] : 0.0f, g, af, hb);
+  }
   if (l >= L) return;
   const float rho = sd.rho[l];
   float4 *__restrict__ qs4 = reinterpret_cast<float4 *>(qS) + 3 * (size_t)l;
@@ -163,32 +319,33 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
     return;
   }
   const int d = l % sd.n_bins;
-  float g[kWin], af[kWin * kMat], hb[kWin * 6], n0[kWin];
-  const float scale = energy_sums_safe<true, CLIP, PB>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb, d);
+  const float scale = MFMA ? energy_sums_rescue<true, CLIP, PB>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb, d)
+                           : energy_sums_safe<true, CLIP, PB>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb, d);
   ray_n0<PB>(sd, d, n0);
 
-  T a[kWin][kMat], cw[kWin], rw[kWin], yw[kWin], sig[kWin];
+  T a[kWin][kMat], cw[kWin], rw[kWin], yw[kWin], sig[kWin], ig[kWin];
 #pragma unroll
   for (int w = 0; w < kWin; ++w) {
     const float cf = c[w * L + l];
     cw[w] = (T)cf;
     rw[w] = (T)(cf - n0[w] * g[w] * scale);
     yw[w] = (T)y[w * L + l];
-    const T ig = T(1) / (T)g[w];
+    ig[w] = T(1) / (T)g[w];
 #pragma unroll
-    for (int m = 0; m < kMat; ++m) a[w][m] = (T)af[w * kMat + m] * ig;
+    for (int m = 0; m < kMat; ++m) a[w][m] = (T)af[w * kMat + m] * ig[w];
   }
   // step lengths and the per-ray preconditioner terms
   T extra[6];
   const T lr = (T)lambda * (T)rho;
   if (BLOCK) {
+    const T ilr = T(1) / lr;
 #pragma unroll
     for (int j = 0; j < 6; ++j) extra[j] = T(0);
 #pragma unroll
     for (int w = 0; w < kWin; ++w) {
       const T nrm = sqrt(a[w][0] * a[w][0] + a[w][1] * a[w][1] + a[w][2] * a[w][2]);
-      sig[w] = T(1) / (lr * nrm);
       const T inv = T(1) / nrm;
+      sig[w] = ilr * inv;
 #pragma unroll
       for (int m = 0; m < 3; ++m)
 #pragma unroll
@@ -212,18 +369,17 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
   } else {
     T rg[kWin];
 #pragma unroll
-    for (int w = 0; w < kWin; ++w) rg[w] = rw[w] / (T)g[w];
+    for (int w = 0; w < kWin; ++w) rg[w] = rw[w] * ig[w];
     T h[6], hp[6];
     ray_hessian<T>(a, cw, rg, hb, h);
     clip_negative_curvature<T, sizeof(T) == 8 ? 8 : 6>(h, hp);
     // column equilibration of G
-    T cn[3], gt[kWin][kMat];
+    T ic[3], gt[kWin][kMat];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      cn[m] = sqrt(a[0][m] * a[0][m] + a[1][m] * a[1][m] + a[2][m] * a[2][m] + a[3][m] * a[3][m]);
-      const T ic = T(1) / cn[m];
+      ic[m] = T(1) / sqrt(a[0][m] * a[0][m] + a[1][m] * a[1][m] + a[2][m] * a[2][m] + a[3][m] * a[3][m]);
 #pragma unroll
-      for (int w = 0; w < kWin; ++w) gt[w][m] = a[w][m] * ic;
+      for (int w = 0; w < kWin; ++w) gt[w][m] = a[w][m] * ic[m];
     }
     T gram[6];
 #pragma unroll
@@ -238,20 +394,20 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
     T gi[3][3];
     spd3_inverse<T>(gram, gi);
     // P~ = Sigma^-1/2 G~ Gram^-1   (rows w)
-    T ss[kWin], P[kWin][3];
+    T ss[kWin], is[kWin], P[kWin][3];
 #pragma unroll
     for (int w = 0; w < kWin; ++w) {
       ss[w] = sqrt(sig[w]);
-      const T is = T(1) / ss[w];
+      is[w] = T(1) / ss[w];
 #pragma unroll
-      for (int n = 0; n < 3; ++n) P[w][n] = (gt[w][0] * gi[0][n] + gt[w][1] * gi[1][n] + gt[w][2] * gi[2][n]) * is;
+      for (int n = 0; n < 3; ++n) P[w][n] = (gt[w][0] * gi[0][n] + gt[w][1] * gi[1][n] + gt[w][2] * gi[2][n]) * is[w];
     }
     // H^ = C^-1 H^+ C^-1
     T Hh[3][3];
 #pragma unroll
     for (int m = 0; m < 3; ++m)
 #pragma unroll
-      for (int n = 0; n < 3; ++n) Hh[m][n] = hp[m <= n ? ut(m, n) : ut(n, m)] / (cn[m] * cn[n]);
+      for (int n = 0; n < 3; ++n) Hh[m][n] = hp[m <= n ? ut(m, n) : ut(n, m)] * (ic[m] * ic[n]);
     // M = P~ H^ P~^T
     T PH[kWin][3], Mm[kWin][kWin];
 #pragma unroll
@@ -264,7 +420,7 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
       for (int v = 0; v < kWin; ++v) Mm[w][v] = PH[w][0] * P[v][0] + PH[w][1] * P[v][1] + PH[w][2] * P[v][2];
     T bt[kWin], z[kWin];
 #pragma unroll
-    for (int w = 0; w < kWin; ++w) bt[w] = (rw[w] - yw[w]) / ss[w];
+    for (int w = 0; w < kWin; ++w) bt[w] = (rw[w] - yw[w]) * is[w];
     unit_plus_psd4_solve<T>(Mm, bt, z);
 #pragma unroll
     for (int w = 0; w < kWin; ++w) yw[w] = yw[w] + ss[w] * z[w];
