@@ -309,6 +309,29 @@ def test_mocca_one_step_intermediates(tiny):
         assert np.linalg.norm(df_gpu[m] - df_ref[m]) <= 1e-3 * np.linalg.norm(df_ref[m])
 
 
+def test_mocca_one_step_negative_paths(tiny):
+    """One iteration from maps with negative projections (z < 0: softexp's
+    linear branch, where softexp' and softexp'' differ from softexp): y and f
+    match the oracle's parts."""
+    from paper_1801_06263_amd import Params
+    pr, X, c, plan = tiny
+    lam = 3e-7
+    rng = np.random.default_rng(10)
+    f0 = (-0.5 * pr.f_true * (1 + 0.05 * rng.standard_normal(pr.f_true.shape))).astype(np.float32)
+    p0 = X @ f0.reshape(3, -1).T.astype(np.float64)
+    assert (p0 @ pr.spec.mu < 0).mean() > 0.5  # most (ray, energy) pairs on the linear branch
+    parts = {}
+    st0 = omocca.initial_state(3, X.shape[1], X.shape[0], 4, f0.astype(np.float64))
+    omocca.mocca_step(X, np.asarray(X.sum(axis=1)).ravel(), st0, c, pr.spec, lam, "block", "clip", parts)
+    st = plan.new_state(dev(sino(c, pr.geom)), dev(f0))
+    plan.mocca_iterate(st, Params(lam, "block", "clip", True), 1)
+    assert normwise(host(st.y).reshape(4, -1).T, parts["y"]) <= 1e-4
+    df_gpu = host(st.f).reshape(3, -1) - f0.reshape(3, -1)
+    df_ref = parts["f"] - f0.reshape(3, -1)
+    for m in range(3):
+        assert np.linalg.norm(df_gpu[m] - df_ref[m]) <= 1e-3 * np.linalg.norm(df_ref[m])
+
+
 def test_mocca_is_deterministic(tiny):
     from paper_1801_06263_amd import Params
     pr, X, c, plan = tiny
