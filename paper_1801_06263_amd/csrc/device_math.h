@@ -42,6 +42,32 @@ __device__ __forceinline__ float chord_weight(double nx, double ny, float a, flo
   return __builtin_amdgcn_fmed3f(t, 0.0f, hmax);  // clamp to [0, hmax]
 }
 
+// ---------------------------------------------------------------- helpers
+
+// floor(x) as an integer in one instruction; x is finite and in int range
+// (a NaN gives 0)
+__device__ __forceinline__ int floor_to_int(float x) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+// min(max(x, 0), hi) for uniform hi >= 0 in one instruction
+__device__ __forceinline__ int clamp_0_hi(int x, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
+  return r;
+}
+
+// A copy of a (uniform) value held in a VGPR: lets a loop use it as the
+// vector operand of an instruction that already reads one SGPR, instead of
+// moving it from the SGPR on every iteration.
+__device__ __forceinline__ float in_vgpr(float x) {
+  float r;
+  asm("v_mov_b32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 // ---------------------------------------------------------------- softexp
 //
 // softexp(x) = exp(x) for x <= 0 and x + 1 for x > 0 (Sec. II).  With

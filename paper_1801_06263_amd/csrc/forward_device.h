@@ -76,13 +76,6 @@ __device__ __forceinline__ int wave_max(int x) {
 // kFpUnroll - 1 columns, which the zero border (kPad >= kFpUnroll) absorbs.
 constexpr int kFpUnroll = 4;
 
-// floor(x) as an integer in one instruction; x is finite and in int range
-// (a NaN gives 0)
-__device__ __forceinline__ int floor_to_int(float x) {
-  int r;
-  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-  return r;
-}
 static_assert(kPad >= kFpUnroll, "border must cover the unrolled tail");
 template <bool XMAJOR, bool THIRD, bool COUNT>
 __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4 *__restrict__ img, double s_u,

@@ -61,7 +61,7 @@ struct BinLDS {
 struct ViewTile {
   int d0, d1;    // bins whose rays can meet the tile
   float hw;      // bound on a pixel's shadow half-width (bins), incl. margin; < 0: use [d0, d1]
-  float off;     // cbin - hw - d0: a pixel's window starts at ceil(bin_scale t + off) (staged index)
+  float off;     // cbin - hw - d0 + 1: a pixel's window starts at floor(bin_scale t + off) (staged index)
   int nst;       // staged bins, max(0, d1 - d0 + 1)
   int K;         // window length, min(nst, floor(2 hw) + 1); nst when hw < 0
   int pad0, pad1;
@@ -107,7 +107,7 @@ __device__ __forceinline__ void tile_view_bounds(const ScanDesc &sd, const ViewG
     const float A = fmaxf(fabsf(-vg.sb + vg.cb * tmin), fabsf(-vg.sb + vg.cb * tmax));
     const float B = fmaxf(fabsf(vg.cb + vg.sb * tmin), fabsf(vg.cb + vg.sb * tmax));
     out.hw = 0.5f * (A + B) / dmin * (1.0f + 1.5f / dmin) * sd.bin_scale + 0.02f;
-    out.off = sd.cbin - out.hw - (float)out.d0;
+    out.off = sd.cbin - out.hw - (float)out.d0 + 1.0f;
     out.K = min(out.nst, (int)floorf(2.0f * out.hw) + 1);
   } else {
     out.hw = -1.0f;
@@ -364,6 +364,7 @@ __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int 
   const unsigned nb = (unsigned)sd.n_bins, q_stride = (unsigned)q_stride_i;
   const float X = (float)ix - sd.c0;  // centred, for the detector projection
   const float Y = (float)iy - sd.c0;
+  const float sid = in_vgpr(sd.sid_px);
   const double fx = (double)ix, fy = (double)iy;
   const int su = tid >> 6, sl = tid & 63;  // staged slot: view su of the group, bin sl
   static_assert(kBpGroup * 64 == kBpThreads && kBpSlot == 64, "one wave per view, one lane per bin");
@@ -404,21 +405,28 @@ __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int 
         nst[u] = g0 + u < cnt ? min(__builtin_amdgcn_readfirstlane(vt[u].nst), kBpSlot) : 0;
         kmax = max(kmax, min(__builtin_amdgcn_readfirstlane(vt[u].K), nst[u]));
         const float num = __fmaf_rn(vg[u].cb, Y, -vg[u].sb * X);
-        const float den = __fmaf_rn(-vg[u].sb, Y, __fmaf_rn(-vg[u].cb, X, sd.sid_px));
+        const float den = __fmaf_rn(-vg[u].sb, Y, __fmaf_rn(-vg[u].cb, X, sid));
         t[u] = __fmaf_rn(num * __builtin_amdgcn_rcpf(den), sd.bin_scale, vt[u].off);
         dx[u] = vg[u].sx - fx;
         dy[u] = vg[u].sy - fy;
       }
       // window u: [s, s + kmax) inside [0, max(nst, kmax)) within the slot,
-      // covering the staged part of the pixel's shadow (at most K <= kmax bins)
+      // starting at floor(tau - hw) + 1: it covers the staged part of the
+      // pixel's shadow, the integers inside (tau - hw, tau + hw) (at most
+      // K <= kmax of them)
+      const BinLDS *wb[kBpGroup];  // window starts (s < 64: 24-bit multiplies)
 #pragma unroll
-      for (int u = 0; u < kBpGroup; ++u) s[u] = min(max((int)ceilf(t[u]), 0), max(0, nst[u] - kmax));
+      for (int u = 0; u < kBpGroup; ++u) {
+        s[u] = clamp_0_hi(floor_to_int(t[u]), max(0, nst[u] - kmax));
+        wb[u] = reinterpret_cast<const BinLDS *>(reinterpret_cast<const char *>(&sh.gbins[u][0]) +
+                                                 __umul24((unsigned)s[u], (unsigned)sizeof(BinLDS)));
+      }
       for (int i = 0; i < kmax; ++i) {
 #pragma unroll
         for (int u = 0; u < kBpGroup; u += 2) {
           BinLDS e0, e1;  // two views' reads in flight before the first weight
-          load_bin<NCH>(sh.gbins[u][s[u] + i], e0);
-          load_bin<NCH>(sh.gbins[u + 1][s[u + 1] + i], e1);
+          load_bin<NCH>(wb[u][i], e0);
+          load_bin<NCH>(wb[u + 1][i], e1);
           accumulate_bin<NCH>(e0, dx[u], dy[u], part);
           accumulate_bin<NCH>(e1, dx[u + 1], dy[u + 1], part);
         }
