@@ -13,14 +13,14 @@
 // one bin per lane, up to 64); slots past a view's shadow hold a null record
 // whose weight is exactly 0.  The loads of the next group are issued before
 // the current group is processed and stored after it, so a group costs two
-// barriers.  A pixel's non-zero weights in a view lie on the bins inside
-// [tau - hw, tau + hw], tau being its centre's detector position: at most
-// K = floor(2 hw) + 1 consecutive bins.  Every thread reads, in each of the
-// group's views, a window of Kmax = max K of the group staged bins starting
-// at ceil(tau - hw), clamped into the staged range; the bins of a window
-// outside the pixel's shadow have weight exactly 0.  Kmax is uniform over the
-// workgroup, so the loop carries no per-lane bounds or divergence, and the
-// four views' windows are independent work within a step.
+// barriers.  A pixel's non-zero weights in a view lie on the bins strictly
+// inside (tau - hw, tau + hw), tau being its centre's detector position: at
+// most K = floor(2 hw) + 1 consecutive bins.  Every thread reads, in each of
+// the group's views, a window of Kmax = max K of the group staged bins
+// starting at floor(tau - hw) + 1, clamped into the staged range; the bins of
+// a window outside the pixel's shadow have weight exactly 0.  Kmax is uniform
+// over the workgroup, so the loop carries no per-lane bounds or divergence,
+// and the four views' windows are independent work within a step.
 //
 // Wide path (some tile shadow exceeds 62 bins; chosen by the plan): one view
 // at a time, up to 128 bins staged by all four waves, each thread looping
