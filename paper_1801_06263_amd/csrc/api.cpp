@@ -146,8 +146,8 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   const double h = g.pixel_cm;
 
   // per-view source position and per-ray line parameters, pixel index
-  // coordinates (pixel (ix, iy) centred at (ix, iy)): unit normals in FP64,
-  // the trapezoid constants rounded to FP32
+  // coordinates (pixel (ix, iy) centred at (ix, iy)): normals scaled by
+  // kappa in FP64, the trapezoid constants rounded to FP32
   const double c0 = 0.5 * (N - 1);
   std::vector<RayLine> rays(L);
   std::vector<ViewGeom> views(V);
@@ -170,7 +170,7 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
       const double hmax = h / std::max(anx, any);
       const double prod = anx * any;
       const double kappa = (prod * 1e30 > h) ? h / prod : 1e30;
-      rays[(size_t)v * D + d] = RayLine{nx, ny, (float)a, (float)hmax, (float)kappa, 0.0f};
+      rays[(size_t)v * D + d] = RayLine{nx * kappa, ny * kappa, (float)(a * kappa), (float)hmax, (float)kappa, 0.0f};
     }
   }
   // spectral table: shared responses folded with mu, or (per detector bin)

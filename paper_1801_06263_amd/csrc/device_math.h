@@ -24,22 +24,26 @@ namespace osscir {
 //   hmax  = 1 / max(|nx|, |ny|)         (chord through a full column/row)
 // all multiplied by the pixel size to give centimetres.  This is the exact
 // line-intersection length X_{l,k} (the chord of the square, Sec. II's
-// "projection along ray l"), evaluated branch-free.
+// "projection along ray l"), evaluated branch-free.  The ray table holds
+// the normal and the half-width already scaled by kappa, so the trapezoid is
+// min(hmax, max(0, a kappa - |sig kappa|)): one subtraction and one clamp.
 //
 // Coordinates are pixel units with pixel (ix, iy) centred at (ix, iy); the
 // caller passes dx = Sx - ix, dy = Sy - iy in FP64 (sig is a difference of
-// numbers as large as the source distance), sig is rounded once to FP32 and
-// the trapezoid is FP32.
+// numbers as large as the source distance), sig kappa is rounded once to
+// FP32 and the trapezoid is FP32.
 struct RayLine {
-  double nx, ny;
-  float a, hmax, kappa, pad;
+  double nxk, nyk;  // kappa nx, kappa ny
+  float ak, hmax;   // kappa a, hmax
+  float kappa, pad;
 };
 
-__device__ __forceinline__ float chord_weight(double nx, double ny, float a, float hmax, float kappa, double dx,
-                                              double dy) {
-  const double sig = fma(nx, dx, ny * dy);
-  const float t = (a - fabsf((float)sig)) * kappa;
-  return __builtin_amdgcn_fmed3f(t, 0.0f, hmax);  // clamp to [0, hmax]
+// zero: 0.0f (a caller reading the ray from a record may pass the record's
+// stored zero instead of the constant, with the same result)
+__device__ __forceinline__ float chord_weight(double nxk, double nyk, float ak, float hmax, double dx, double dy,
+                                              float zero = 0.0f) {
+  const double sigk = fma(nxk, dx, nyk * dy);
+  return __builtin_amdgcn_fmed3f(ak - fabsf((float)sigk), zero, hmax);  // clamp to [0, hmax]
 }
 
 // ---------------------------------------------------------------- helpers

@@ -116,16 +116,16 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
       const double dv0 = s_v - fv0;
       const double dv1 = s_v - (fv0 + 1.0);
       if (XMAJOR) {
-        w[k][0] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, du, dv0);
-        w[k][1] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, du, dv1);
+        w[k][0] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, du, dv0);
+        w[k][1] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, du, dv1);
       } else {
-        w[k][0] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, dv0, du);
-        w[k][1] = chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, dv1, du);
+        w[k][0] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, dv0, du);
+        w[k][1] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, dv1, du);
       }
       if (THIRD) {
         const double dve = s_v - (double)ive;
-        w[k][2] = XMAJOR ? chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, du, dve)
-                         : chord_weight(ray.nx, ray.ny, ray.a, ray.hmax, ray.kappa, dve, du);
+        w[k][2] = XMAJOR ? chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, du, dve)
+                         : chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, dve, du);
       }
       // a column index past the image reads the zero border (w * 0 adds +0 to
       // the sums); only the counting pass must drop its weights
@@ -169,18 +169,19 @@ __device__ __forceinline__ void forward_rays(const ScanDesc &sd, const float4 *_
   const int n = sd.n;
   const bool active = d < sd.n_bins;
   const ViewGeom vg = load_uniform(sd.views + v);
-  RayLine ray{1.0, 0.0, 0.0f, 0.0f, 0.0f, 0.0f};
+  RayLine ray{1.0, 0.0, 0.0f, 0.0f, 1.0f, 0.0f};
   bool xmajor = true, near45 = false;
   float slope = 0.0f, base = 0.0f;
   int iu_lo = n, iu_hi = -1;
   if (active) {
     ray = sd.rays[v * sd.n_bins + d];
-    // the line in index coordinates: nx ix + ny iy = nx sx + ny sy
-    const double sidx = ray.nx * vg.sx + ray.ny * vg.sy;
-    xmajor = fabs(ray.ny) >= fabs(ray.nx);
-    const double nu = xmajor ? ray.nx : ray.ny;  // along the walked axis
-    const double nv = xmajor ? ray.ny : ray.nx;  // along the minor axis, |nv| >= 1/sqrt 2
-    near45 = (fabs(nv) - fabs(nu)) < 2e-3;
+    // the line in index coordinates: nx ix + ny iy = nx sx + ny sy (here
+    // with the normal scaled by kappa > 0, which leaves the line unchanged)
+    const double sidx = ray.nxk * vg.sx + ray.nyk * vg.sy;
+    xmajor = fabs(ray.nyk) >= fabs(ray.nxk);
+    const double nu = xmajor ? ray.nxk : ray.nyk;  // along the walked axis
+    const double nv = xmajor ? ray.nyk : ray.nxk;  // along the minor axis, |nv| >= |n| / sqrt 2
+    near45 = (fabs(nv) - fabs(nu)) < 2e-3 * (double)ray.kappa;  // |nv| - |nu| < 2e-3 for the unit normal
     slope = (float)(-nu / nv);
     base = (float)(sidx / nv);
     // walked indices where the crossing lies in (-1.5, n + 0.5), widened by one

@@ -51,8 +51,8 @@ constexpr int kBpSlot = 64;       // staged bins per view of a group (one lane e
 // eight consecutive bins on 32 distinct LDS banks; a power-of-two stride
 // would fold them onto two bank groups.
 struct BinLDS {
-  double2 n;   // nx, ny
-  float4 w0;   // a, hmax, kappa, q8
+  double2 n;   // kappa nx, kappa ny
+  float4 w0;   // kappa a, hmax, 0, q8
   float4 w1;   // q0..q3
   float4 w2;   // q4..q7
   float4 pad;
@@ -174,8 +174,8 @@ __device__ __forceinline__ void bin_store(const BinRegs<NCH> &b, BinLDS &e) {
   float qq[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) qq[c] = c < NCH ? b.q[c] : 0.0f;
-  e.n = make_double2(b.r.nx, b.r.ny);
-  e.w0 = make_float4(b.r.a, b.r.hmax, b.r.kappa, qq[8]);
+  e.n = make_double2(b.r.nxk, b.r.nyk);
+  e.w0 = make_float4(b.r.ak, b.r.hmax, 0.0f, qq[8]);
   e.w1 = make_float4(qq[0], qq[1], qq[2], qq[3]);
   if (NCH > 4) e.w2 = make_float4(qq[4], qq[5], qq[6], qq[7]);
 }
@@ -193,7 +193,7 @@ template <int NCH>
 __device__ __forceinline__ void accumulate_bin(const BinLDS &e, double dx, double dy, float part[NCH]) {
   const double2 nn = e.n;
   const float4 w0 = e.w0;
-  const float w = chord_weight(nn.x, nn.y, w0.x, w0.y, w0.z, dx, dy);
+  const float w = chord_weight(nn.x, nn.y, w0.x, w0.y, dx, dy, w0.z);  // w0.z = 0: the record is read whole
   float qv[9];
   const float4 w1 = e.w1;
   qv[0] = w1.x; qv[1] = w1.y; qv[2] = w1.z; qv[3] = w1.w;
@@ -421,7 +421,8 @@ __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int 
         wb[u] = reinterpret_cast<const BinLDS *>(reinterpret_cast<const char *>(&sh.gbins[u][0]) +
                                                  __umul24((unsigned)s[u], (unsigned)sizeof(BinLDS)));
       }
-      for (int i = 0; i < kmax; ++i) {
+      const int kmx = __builtin_amdgcn_readfirstlane(kmax);  // uniform trip count: a scalar loop
+      for (int i = 0; i < kmx; ++i) {
 #pragma unroll
         for (int u = 0; u < kBpGroup; u += 2) {
           BinLDS e0, e1;  // two views' reads in flight before the first weight
