@@ -34,14 +34,16 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 
 # Algorithmic work per unit (lane operations, an FMA counts one):
-#   chord weight of one (ray, pixel) pair: 2 FMA (signed distance) + |.|-sub,
-#     mul, max, min = 6; forward projection adds 3 FMA, back-projection 9.
+#   chord weight of one (ray, pixel) pair, the line's normal and half-width
+#     scaled by the trapezoid's slope in the ray table: 2 FMA (signed
+#     distance) + |.|-sub, max, min = 5; forward projection adds 3 FMA,
+#     back-projection 9.
 #   one (ray, energy) pair of the energy loop: z 3, exp 2, softexp selects 3,
 #     window sums 4, Jacobian rows 12, curvature sums 24 (clip) -> 48; window
 #     curvature drops the 24 and one select -> 23.
 #   per-ray tail: step lengths, Hessian, eigen-clip, 4x4 dual solve ~ 400
 #     (clip) / 60 (window); per-pixel 3x3 equilibrated solve + update ~ 60.
-OPS = {"w": 6, "fp_fma": 3, "bp_fma_block": 9, "bp_fma_diag": 6, "energy_clip": 48, "energy_window": 23,
+OPS = {"w": 5, "fp_fma": 3, "bp_fma_block": 9, "bp_fma_diag": 6, "energy_clip": 48, "energy_window": 23,
        "tail_clip": 400, "tail_window": 60, "pixel": 60}
 # Algorithmic HBM bytes per iteration (FP32): per ray c 4 + y in/out 8 + rho 1
 # + p write/read 6 + qS write/read 18 words; per pixel f, fbar read and written 12.

@@ -413,17 +413,24 @@ int check_iter(osscir_plan plan, const osscir_params *params, const osscir_state
   return OSSCIR_OK;
 }
 
-int run_stage(const ScanDesc &sd, const IterArgs &a, osscir_state *state, int stage, hipStream_t st) {
+// packed: the workspace's packed images already hold fbar (written by the
+// previous iteration's primal step); pack_next: the primal step writes
+// fbar' into them for the next iteration
+int run_stage(const ScanDesc &sd, const IterArgs &a, osscir_state *state, int stage, hipStream_t st,
+              bool packed = false, bool pack_next = false) {
   switch (stage) {
     case 0:
-      OSSCIR_HIP(launch_forward(sd, state->fbar, 3, a.p, a.pack, st), "mocca: forward projection");
+      if (packed)
+        OSSCIR_HIP(launch_forward_packed(sd, a.pack, a.p, st), "mocca: forward projection");
+      else
+        OSSCIR_HIP(launch_forward(sd, state->fbar, 3, a.p, a.pack, st), "mocca: forward projection");
       break;
     case 1:
       OSSCIR_HIP(launch_spectral_dual(sd, a.p, state->c, state->y, a.qS, a.lam, a.clip, a.block, a.fp64, st),
                  "mocca: spectral model and dual step");
       break;
     case 2:
-      OSSCIR_HIP(launch_back_primal(sd, a.qS, state->f, state->fbar, a.lam, a.block, a.fp64, st),
+      OSSCIR_HIP(launch_back_primal(sd, a.qS, state->f, state->fbar, a.lam, a.block, pack_next ? a.pack : nullptr, st),
                  "mocca: back-projection and primal step");
       break;
     default:
@@ -442,9 +449,14 @@ int osscir_mocca_iterate(osscir_plan plan, const osscir_params *params, osscir_s
   if (n_iter < 0) return fail(OSSCIR_EINVAL, "n_iter < 0");
   const ScanDesc &sd = plan->sd;
   hipStream_t st = (hipStream_t)stream;
+  // without D_TPL (whose forward projection reuses the packed images) the
+  // primal step packs fbar' for the next iteration, so only the first
+  // iteration of the call runs the packing kernel
+  const bool chain = dtpl == nullptr;
   for (int it = 0; it < n_iter; ++it) {
+    const bool packed = chain && it > 0, pack_next = chain && it + 1 < n_iter;
     for (int stage = 0; stage < 3; ++stage)
-      if ((rc = run_stage(sd, a, state, stage, st))) return rc;
+      if ((rc = run_stage(sd, a, state, stage, st, packed, pack_next))) return rc;
     if (dtpl)
       OSSCIR_HIP(launch_dtpl(sd, state->f, state->c, a.p, a.pack, a.partial, dtpl + it, st), "mocca: D_TPL");
   }

@@ -12,6 +12,10 @@ size_t pack_scratch_bytes(const ScanDesc &sd);
 // pack: device scratch of pack_scratch_bytes().
 hipError_t launch_forward(const ScanDesc &sd, const float *f, int nch, float *p, void *pack, hipStream_t st);
 
+// p[c][l] for c < 3 from images already packed by launch_pack (or by the
+// primal step's packing epilogue).
+hipError_t launch_forward_packed(const ScanDesc &sd, const void *pack, float *p, hipStream_t st);
+
 // Packs up to 3 channels of f into the two padded images of pack (the
 // layout launch_forward uses): row-contiguous copy first, then the
 // column-contiguous one.

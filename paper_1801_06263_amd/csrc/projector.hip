@@ -94,6 +94,14 @@ hipError_t launch_forward(const ScanDesc &sd, const float *f, int nch, float *p,
   return hipSuccess;
 }
 
+hipError_t launch_forward_packed(const ScanDesc &sd, const void *pack, float *p, hipStream_t st) {
+  const size_t np = (size_t)sd.n + 2 * kPad;
+  const float4 *pk_xy = reinterpret_cast<const float4 *>(pack);
+  hipLaunchKernelGGL(k_forward<false>, dim3(forward_blocks(sd)), dim3(kFpBlock), 0, st, sd, pk_xy, pk_xy + np * np, p,
+                     (int)sd.n_rays, 3);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack(const ScanDesc &sd, const float *f, int nch, void *pack, hipStream_t st) {
   const size_t np = (size_t)sd.n + 2 * kPad;
   float4 *pk_xy = reinterpret_cast<float4 *>(pack);

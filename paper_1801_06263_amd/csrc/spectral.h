@@ -13,9 +13,11 @@ hipError_t launch_spectral_model(const ScanDesc &sd, const float *p, const float
 hipError_t launch_spectral_dual(const ScanDesc &sd, const float *p, const float *c, float *y, float *qS,
                                 float lambda, bool clip, bool block, bool fp64, hipStream_t st);
 
-// back-projection of qS fused with the primal step and the extrapolation.
+// back-projection of qS fused with the primal step and the extrapolation;
+// pack (optional): packed images (launch_pack's layout, borders already
+// zero) that receive fbar' for the next forward projection.
 hipError_t launch_back_primal(const ScanDesc &sd, const float *qS, float *f, float *fbar, float lambda, bool block,
-                              bool fp64, hipStream_t st);
+                              void *pack, hipStream_t st);
 
 // sigma [4][L], per-ray terms (scratch, 6 or 3 channels) and the pixel
 // steps out_img (T^-1 upper triangles or tau).

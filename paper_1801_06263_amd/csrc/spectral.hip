@@ -129,16 +129,20 @@ __global__ void k_scale_steps(int count, float lambda, float *__restrict__ v) {
 
 // ---------------------------------------------------------------- primal
 
-template <bool BLOCK, bool WIDE>
+// PACK: fbar' is also written into the packed images of the next forward
+// projection (pk_xy, pk_yx: interior pixels; borders already zero)
+template <bool BLOCK, bool WIDE, bool PACK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_back_primal(ScanDesc sd, const float *__restrict__ qS,
-                                                      float *__restrict__ f, float *__restrict__ fbar, float lambda) {
+                                                      float *__restrict__ f, float *__restrict__ fbar, float lambda,
+                                                      float4 *__restrict__ pk_xy, float4 *__restrict__ pk_yx) {
   __shared__ BpShared sh;
   const int nt = (sd.n + kBpTile - 1) / kBpTile;
   int item;
   if (!xcd_item(nt * nt, item)) return;
   const int t = as_const(sd.tile_order)[item];
   const int tile_y = t / nt;
-  back_primal_tile<BLOCK, WIDE, false>(sd, qS, f, fbar, lambda, t - tile_y * nt, tile_y, sh, PrimalEpilogue{});
+  back_primal_tile<BLOCK, WIDE, PACK>(sd, qS, f, fbar, lambda, t - tile_y * nt, tile_y, sh,
+                                      PrimalEpilogue{pk_xy, pk_yx, nullptr});
 }
 
 // ---------------------------------------------------------------- D_TPL
@@ -253,14 +257,26 @@ hipError_t launch_spectral_dual(const ScanDesc &sd, const float *p, const float 
 }
 
 hipError_t launch_back_primal(const ScanDesc &sd, const float *qS, float *f, float *fbar, float lambda, bool block,
-                              bool fp64, hipStream_t st) {
-  (void)fp64;
-#define OSSCIR_BP(B, W) hipLaunchKernelGGL((k_back_primal<B, W>), pix_grid(sd), dim3(256), 0, st, sd, qS, f, fbar, lambda)
+                              void *pack, hipStream_t st) {
+  const size_t np = (size_t)sd.n + 2 * kPad;
+  float4 *pk_xy = reinterpret_cast<float4 *>(pack);
+  float4 *pk_yx = pack ? pk_xy + np * np : nullptr;
+#define OSSCIR_BP(B, W, P)                                                                                   \
+  hipLaunchKernelGGL((k_back_primal<B, W, P>), pix_grid(sd), dim3(256), 0, st, sd, qS, f, fbar, lambda, pk_xy, \
+                     pk_yx)
+#define OSSCIR_BP2(B, W) \
+  do {                   \
+    if (pack)            \
+      OSSCIR_BP(B, W, true); \
+    else                 \
+      OSSCIR_BP(B, W, false); \
+  } while (0)
   if (block) {
-    if (sd.bp_wide) OSSCIR_BP(true, true); else OSSCIR_BP(true, false);
+    if (sd.bp_wide) OSSCIR_BP2(true, true); else OSSCIR_BP2(true, false);
   } else {
-    if (sd.bp_wide) OSSCIR_BP(false, true); else OSSCIR_BP(false, false);
+    if (sd.bp_wide) OSSCIR_BP2(false, true); else OSSCIR_BP2(false, false);
   }
+#undef OSSCIR_BP2
 #undef OSSCIR_BP
   return hipGetLastError();
 }

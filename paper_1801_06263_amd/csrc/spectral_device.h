@@ -448,14 +448,14 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
 //                 fbar'  = 2 f' - f.
 // The 3x3 solve takes the FP64 sums directly (equilibrated Cholesky).
 //
-// EPI (batched iteration) adds two outputs: fbar' written into the packed
-// images the next forward projection reads (interior only; the zero border
-// is written once when the scan is bound), the column-contiguous copy
-// transposed through LDS; and the tile's FP64 sums of |f' - f|^2 and |f'|^2
-// (fixed-order reduction) for the relative-change stopping rule.
+// EPI adds fbar' written into the packed images the next forward projection
+// reads (interior only; the zero border is written when the images are
+// first packed), the column-contiguous copy transposed through LDS; and, if
+// partial is set (batched iteration), the tile's FP64 sums of |f' - f|^2 and
+// |f'|^2 (fixed-order reduction) for the relative-change stopping rule.
 struct PrimalEpilogue {
   float4 *pk_xy, *pk_yx;
-  double2 *partial;  // this tile's (sum |f' - f|^2, sum |f'|^2)
+  double2 *partial;  // this tile's (sum |f' - f|^2, sum |f'|^2), or null
 };
 
 template <bool BLOCK, bool WIDE, bool EPI>
@@ -500,27 +500,30 @@ __device__ __forceinline__ void back_primal_tile(const ScanDesc &sd, const float
   const int np = sd.n + 2 * kPad;
   const float4 v4 = make_float4(fb[0], fb[1], fb[2], 0.0f);
   if (inside) epi.pk_xy[(size_t)(iy + kPad) * np + (ix + kPad)] = v4;
-  double d2 = 0.0, n2 = 0.0;
+  const bool sums = epi.partial != nullptr;  // uniform
+  if (sums) {
+    double d2 = 0.0, n2 = 0.0;
 #pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    const double dm = (double)fn[m] - (double)fo[m];
-    d2 += dm * dm;
-    n2 += (double)fn[m] * (double)fn[m];
-  }
+    for (int m = 0; m < 3; ++m) {
+      const double dm = (double)fn[m] - (double)fo[m];
+      d2 += dm * dm;
+      n2 += (double)fn[m] * (double)fn[m];
+    }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    d2 += __shfl_xor(d2, o, 64);
-    n2 += __shfl_xor(n2, o, 64);
+    for (int o = 32; o > 0; o >>= 1) {
+      d2 += __shfl_xor(d2, o, 64);
+      n2 += __shfl_xor(n2, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = make_double2(d2, n2);
   }
   sh.tile[ty][tx] = v4;  // the gather's closing barrier has released the staging slots
-  if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = make_double2(d2, n2);
   __syncthreads();
   {
     const int cx = threadIdx.x / kBpTile, ry = threadIdx.x & (kBpTile - 1);  // column cx, row ry of the tile
     const int jx = tile_x * kBpTile + cx, jy = tile_y * kBpTile + ry;
     if (jx < sd.n && jy < sd.n) epi.pk_yx[(size_t)(jx + kPad) * np + (jy + kPad)] = sh.tile[ry][cx];
   }
-  if (threadIdx.x == 0) {
+  if (sums && threadIdx.x == 0) {
     double2 s = sh.red[0];
 #pragma unroll
     for (int w = 1; w < kBpThreads / 64; ++w) {
