@@ -33,18 +33,22 @@ METRIC = "MOCCA iter/s + projector GRays/s at 512^2 x4 windows; batched solves/s
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic work per unit (lane operations, an FMA counts one):
-#   chord weight of one (ray, pixel) pair, the line's normal and half-width
-#     scaled by the trapezoid's slope in the ray table: 2 FMA (signed
-#     distance) + |.|-sub, max, min = 5; forward projection adds 3 FMA,
-#     back-projection 9.
-#   one (ray, energy) pair of the energy loop: z 3, exp 2, softexp selects 3,
-#     window sums 4, Jacobian rows 12, curvature sums 24 (clip) -> 48; window
-#     curvature drops the 24 and one select -> 23.
-#   per-ray tail: step lengths, Hessian, eigen-clip, 4x4 dual solve ~ 400
-#     (clip) / 60 (window); per-pixel 3x3 equilibrated solve + update ~ 60.
-OPS = {"w": 5, "fp_fma": 3, "bp_fma_block": 9, "bp_fma_diag": 6, "energy_clip": 48, "energy_window": 23,
-       "tail_clip": 400, "tail_window": 60, "pixel": 60}
+# Algorithmic work per unit (lane operations, an FMA counts one): what the
+# method computes, counted for a generic evaluation of each step.
+#   exact chord length of one (ray, pixel) pair ~ 12 (clipping the line to
+#     the pixel square); forward projection adds 3 FMA (15 per nonzero of X),
+#     back-projection of [q; S] 9 FMA (21; diagonal SPC [q; h] 6 -> 18).
+#   one (ray, energy) pair of the energy loop ~ 45; per-ray tail (step
+#     lengths, Hessian, eigen-clip, 4x4 dual solve) ~ 600; per pixel (3x3
+#     solve, update, extrapolation) ~ 80.
+#   window curvature (no curvature sums, no eigen-clip): ~ 23 per (ray,
+#     energy) pair and ~ 60 per ray.
+# The library's trapezoid form of the chord takes 5 operations (2 FP64 FMA
+# for the signed distance, |.|-subtract, clamp), so its kernels execute
+# fewer operations per nonzero than these counts (14 instead of 21 in the
+# back-projection).
+OPS = {"fp_nnz": 15, "bp_nnz_block": 21, "bp_nnz_diag": 18, "energy_clip": 45, "energy_window": 23,
+       "tail_clip": 600, "tail_window": 60, "pixel": 80}
 # Algorithmic HBM bytes per iteration (FP32): per ray c 4 + y in/out 8 + rho 1
 # + p write/read 6 + qS write/read 18 words; per pixel f, fbar read and written 12.
 BYTES_PER_RAY = 4 * 37
@@ -468,10 +472,9 @@ def main():
     I = pr.spec.n_energy
     clip = args.curvature == "clip"
     ops = [
-        (OPS["w"] + OPS["fp_fma"]) * nnz,
+        OPS["fp_nnz"] * nnz,
         (OPS["energy_clip" if clip else "energy_window"] * I + OPS["tail_clip" if clip else "tail_window"]) * L,
-        (OPS["w"] + (OPS["bp_fma_block"] if args.precond == "block" else OPS["bp_fma_diag"])) * nnz
-        + OPS["pixel"] * N * N,
+        OPS["bp_nnz_block" if args.precond == "block" else "bp_nnz_diag"] * nnz + OPS["pixel"] * N * N,
     ]
     dom = max(range(3), key=lambda s: stage_ms[s])
     achieved = ops[dom] / (stage_ms[dom] * 1e-3) / 1e12
