@@ -435,6 +435,15 @@ def main():
     finite = bool(torch.isfinite(state.f).all().item() and torch.isfinite(state.y).all().item())
     print(f"[bench] {ms_per_step:.3f} ms/iteration ({t_wall:.2f}s wall for {args.steps}), state finite={finite}",
           file=sys.stderr, flush=True)
+    # the spread over repeated runs: median of 5 runs of 100 iterations
+    runs = []
+    for _ in range(5):
+        e0.record()
+        plan.mocca_iterate(state, params, 100)
+        e1.record()
+        torch.cuda.synchronize()
+        runs.append(100.0 / (e0.elapsed_time(e1) * 1e-3))
+    runs.sort()
 
     # per-kernel durations: the same iterations stage by stage, events on the library's stream
     stage_ms = [0.0, 0.0, 0.0]
@@ -500,6 +509,7 @@ def main():
         "projector": {"fp_grays_s": round(L / (fp_ms * 1e-3) / 1e9, 3), "fp_ms_3ch": round(fp_ms, 4),
                       "bp_grays_s": round(L / (bp_ms * 1e-3) / 1e9, 3), "bp_ms_9ch": round(bp_ms, 4)},
         "stages_ms": {KERNEL_NAMES[s]: round(stage_ms[s], 4) for s in range(3)},
+        "runs_5x100_iter_s": {"median": round(runs[2], 1), "min": round(runs[0], 1), "max": round(runs[4], 1)},
         "roofline": {"bound": "alu", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 3),
                      "peak": round(PEAK_VALU_TOPS, 2), "unit": "Top/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
                      "traffic": traffic},
