@@ -371,8 +371,9 @@ def serving_leg(n_requests: int, rate: float, per_tick: int, batch_cfg=None, see
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: multi-GPU runs are not part of this build "
-              "(slices shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU (--gpus {args.gpus} asked): the library runs a scan on one GPU; "
+              "independent slices would shard across GPUs with no exchange, which is not implemented",
+              file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
