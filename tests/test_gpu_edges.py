@@ -1,6 +1,8 @@
 """Edge cases of the GPU library: empty iteration counts, zero counts, rays
 that miss the image, single-pixel / single-view / single-bin scans, one and
-512 energies, a 2048^2 image, and argument errors reported through the C ABI."""
+512 energies, a 2048^2 image, the largest image (4096^2) and ray count
+(just under 2^27 rays) a plan accepts, and argument errors reported through
+the C ABI."""
 import ctypes
 import warnings
 
@@ -117,6 +119,55 @@ def test_large_image_sampled():
         col = pj.pixel_column(geom, ix, iy)
         refb = float(col @ q.ravel().astype(np.float64))
         assert abs(b[iy, ix] - refb) <= 1e-5 * abs(refb)
+
+
+def test_maximum_image_sampled():
+    """n = 4096, the largest image a plan accepts (32 views x 4096 bins): ray
+    lengths against the closed-form chord of the image square, a forward
+    projection at one view against the oracle, the back-projection at
+    sampled pixels (corner and edge pixels included)."""
+    n, V, D = 4096, 32, 4096
+    geom = synth.make_geometry(n, 40.0, V, D)
+    plan = plan_for(geom, SPEC)
+    assert normwise(host(plan.ray_lengths()).ravel(), pj.square_chord(geom)) <= 1e-5
+    rng = np.random.default_rng(8)
+    f = rng.random((3, n, n), dtype=np.float32)
+    p = host(plan.forward_project(dev(f))).reshape(3, V, D)
+    Xs = pj.system_matrix(geom, views=[13])
+    ref = (Xs @ f.reshape(3, -1).astype(np.float64).T).T
+    assert normwise(p[:, 13], ref) <= 1e-5
+    q = rng.random((1, V, D)).astype(np.float32)
+    b = host(plan.back_project(dev(q))).reshape(n, n)
+    pix = [(2048, 2048), (5, 3000), (4000, 77), (0, 0), (4095, 4095), (4095, 0), (1, 2048)]
+    got = np.array([b[iy, ix] for ix, iy in pix])
+    ref = np.array([pj.pixel_column(geom, ix, iy) @ q.ravel().astype(np.float64) for ix, iy in pix])
+    assert normwise(got, ref) <= 1e-5, (got, ref)
+
+
+def test_maximum_ray_count():
+    """65535 views x 2048 bins, just under the plan's limit of 2^27 rays (a
+    64^2 image whose 16 x 16 tiles shadow hundreds of bins): ray lengths and a
+    forward projection at sampled views against the oracle, and adjointness
+    <X f, q> = <f, X^T q> over every ray (FP64 dots of the FP32 results)."""
+    n, V, D = 64, 65535, 2048
+    geom = synth.make_geometry(n, 20.0, V, D)
+    plan = plan_for(geom, SPEC)
+    views = [0, 1, 32767, 65534]
+    rho = plan.ray_lengths()
+    assert normwise(host(rho[views]).ravel(), pj.square_chord(geom, views=views)) <= 1e-5
+    del rho
+    f = synth.inserts_phantom(n, 20.0).astype(np.float32)
+    p = plan.forward_project(dev(f))
+    Xs = pj.system_matrix(geom, views=views)
+    ref = (Xs @ f.reshape(3, -1).astype(np.float64).T).T
+    assert normwise(host(p[:, views]).reshape(3, -1), ref) <= 1e-5
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    q = torch.rand(1, V, D, device="cuda", generator=gen)
+    b = plan.back_project(q)
+    lhs = float((p[0].double() * q[0].double()).sum().item())
+    rhs = float((dev(f[0]).double() * b[0].double()).sum().item())
+    assert abs(lhs - rhs) <= 1e-6 * abs(lhs), (lhs, rhs)
 
 
 # ---------------------------------------------------------------- argument errors

@@ -343,6 +343,46 @@ def test_mocca_is_deterministic(tiny):
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("precond", ["block", "diag"])
+def test_iterate_call_patterns_agree_bitwise(tiny, precond):
+    """K iterations in one call (the primal step packs fbar' for the next
+    forward projection), K calls of one iteration, K x 3 stage calls, and K
+    iterations with D_TPL (which repacks before every forward projection):
+    identical f, fbar and y."""
+    from paper_1801_06263_amd import Params
+    pr, X, c, plan = tiny
+    prm = Params(3e-7, precond, "clip", True)
+    K = 6
+
+    def fresh():
+        return plan.new_state(dev(sino(c, pr.geom)))
+
+    runs = []
+    st = fresh()
+    plan.mocca_iterate(st, prm, K)
+    runs.append(st)
+    st = fresh()
+    for _ in range(K):
+        plan.mocca_iterate(st, prm, 1)
+    runs.append(st)
+    st = fresh()
+    for _ in range(K):
+        for s in range(3):
+            plan.mocca_stage(st, prm, s)
+    runs.append(st)
+    st = fresh()
+    plan.mocca_iterate(st, prm, K, dtpl=True)
+    runs.append(st)
+    st = fresh()
+    plan.mocca_iterate(st, prm, 2)
+    plan.mocca_iterate(st, prm, K - 2)
+    runs.append(st)
+    torch.cuda.synchronize()
+    for r in runs[1:]:
+        assert torch.equal(r.f, runs[0].f) and torch.equal(r.fbar, runs[0].fbar) and torch.equal(r.y, runs[0].y)
+    assert torch.isfinite(runs[0].f).all()
+
+
 def test_dtpl_parity(tiny):
     from paper_1801_06263_amd import Params
     pr, X, c, plan = tiny
