@@ -160,11 +160,107 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
   s2 += (double)a2;
 }
 
-// One workgroup: rays (v, d0 + threadIdx.x) of one view.
+// The walk of a full wave (all lanes on one major axis, no ray near 45
+// degrees) with the image read through LDS.  In a column the crossing is
+// monotonic in the bin, so the candidate rows of the wave's 64 rays form one
+// run [r0, r1] bounded by its first and last lanes; lane j copies row r0 + j
+// of the packed image straight into the wave's LDS rows (a 16-byte
+// global-to-LDS load: no VGPRs, one copy of a pixel that neighbouring rays
+// share), and each lane then reads its two candidates from LDS.  Where
+// neighbouring rays are under a pixel apart (1024 bins over a 512^2 image:
+// a run of ~35 rows) the texture path moves a third of the bytes of two
+// 12-byte loads per lane.  A step where some lane's candidates fall outside the
+// copied run (a run longer than 64 rows, rounding at the ends) reads the
+// same pixels directly, so the products and their order are exactly those of
+// forward_walk.
+template <bool XMAJOR>
+__device__ __forceinline__ void forward_walk_lds(int lo, int hi, int n, const float4 *__restrict__ img, double s_u,
+                                                 double s_v, float slope, float base, const RayLine &ray, double &s0,
+                                                 double &s1, double &s2, float4 OSSCIR_LDS *wb) {
+  const int np = n + 2 * kPad;
+  const int lane = (int)__lane_id();
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+  int pairs = 0;
+  for (int u = lo; u <= hi; u += kFpUnroll) {
+    int iv0s[kFpUnroll], slot[kFpUnroll];
+    bool bad = false;
+    __builtin_amdgcn_s_waitcnt(0);  // the previous step's reads of wb have completed
+#pragma unroll
+    for (int k = 0; k < kFpUnroll; ++k) {
+      const int uu = u + k;
+      const float ys = __fmaf_rn(slope, (float)uu, base);
+      const int iv0 = floor_to_int(__builtin_amdgcn_fmed3f(ys, -2.0f, (float)n));  // in [-2, n]
+      const int rf = __builtin_amdgcn_readlane(iv0, 0), rl = __builtin_amdgcn_readlane(iv0, 63);
+      const int r0 = min(rf, rl) - 1;  // >= -3
+      const int span = max(rf, rl) - r0 + 2;  // rows r0 .. r1 = max + 1 (lanes past them copy nothing)
+      const int rowp = min(r0 + kPad + lane, np - 1);
+      if (lane < span)
+        __builtin_amdgcn_global_load_lds(img + (size_t)(uu + kPad) * np + rowp, wb + k * 64, 16, 0, 0);
+      iv0s[k] = iv0;
+      slot[k] = iv0 - r0;
+      bad = bad || (unsigned)slot[k] > (unsigned)(min(span, 64) - 2);  // both candidates among the copied rows
+    }
+    float w[kFpUnroll][2];
+#pragma unroll
+    for (int k = 0; k < kFpUnroll; ++k) {
+      const int uu = u + k;
+      const double du = s_u - (double)uu;
+      const double fv0 = (double)iv0s[k];
+      const double dv0 = s_v - fv0;
+      const double dv1 = s_v - (fv0 + 1.0);
+      if (XMAJOR) {
+        w[k][0] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, du, dv0);
+        w[k][1] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, du, dv1);
+      } else {
+        w[k][0] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, dv0, du);
+        w[k][1] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, dv1, du);
+      }
+    }
+    float4 fv[kFpUnroll][2];
+    __builtin_amdgcn_s_waitcnt(0);  // the copies have landed in LDS
+    if (!__any(bad)) {
+      const float4 *wr = (const float4 *)wb;  // generic view of the LDS rows (reads stay ds_read)
+#pragma unroll
+      for (int k = 0; k < kFpUnroll; ++k) {
+        fv[k][0] = wr[k * 64 + slot[k]];
+        fv[k][1] = wr[k * 64 + slot[k] + 1];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kFpUnroll; ++k) {
+        const char *__restrict__ line = reinterpret_cast<const char *>(img + (size_t)(u + k + kPad) * np);
+        const unsigned o0 = (unsigned)(iv0s[k] + kPad) * 16u;
+        fv[k][0] = *reinterpret_cast<const float4 *>(line + o0);
+        fv[k][1] = *reinterpret_cast<const float4 *>(line + o0 + 16u);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kFpUnroll; ++k)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        a0 = __fmaf_rn(w[k][j], fv[k][j].x, a0);
+        a1 = __fmaf_rn(w[k][j], fv[k][j].y, a1);
+        a2 = __fmaf_rn(w[k][j], fv[k][j].z, a2);
+      }
+    if (++pairs == 16 / kFpUnroll) {
+      s0 += (double)a0;
+      s1 += (double)a1;
+      s2 += (double)a2;
+      a0 = a1 = a2 = 0.0f;
+      pairs = 0;
+    }
+  }
+  s0 += (double)a0;
+  s1 += (double)a1;
+  s2 += (double)a2;
+}
+
+// One workgroup: rays (v, d0 + threadIdx.x) of one view.  wb (optional):
+// this wave's kFpUnroll x 64 rows of LDS for forward_walk_lds.
 template <bool COUNT>
 __device__ __forceinline__ void forward_rays(const ScanDesc &sd, const float4 *__restrict__ pk_xy,
                                              const float4 *__restrict__ pk_yx, float *__restrict__ p, int p_stride,
-                                             int nch, int v, int d0) {
+                                             int nch, int v, int d0, float4 OSSCIR_LDS *wb = nullptr) {
   const int d = d0 + threadIdx.x;
   const int n = sd.n;
   const bool active = d < sd.n_bins;
@@ -203,8 +299,18 @@ __device__ __forceinline__ void forward_rays(const ScanDesc &sd, const float4 *_
   const int hi = __builtin_amdgcn_readfirstlane(wave_max(iu_hi));
   const bool any45 = __any(near45);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  // the LDS walk needs every lane of the wave on it (all active, one major
+  // axis): each lane copies a row for the others
+  const bool full = __builtin_amdgcn_read_exec() == ~0ull;
+  const bool lds_walk =
+      !COUNT && wb != nullptr && full && !any45 && __all(active) && (__all(xmajor) || __all(!xmajor));
   if (active) {
-    if (xmajor) {
+    if (lds_walk) {
+      if (xmajor)
+        forward_walk_lds<true>(lo, hi, n, pk_yx, vg.sx, vg.sy, slope, base, ray, a0, a1, a2, wb);
+      else
+        forward_walk_lds<false>(lo, hi, n, pk_xy, vg.sy, vg.sx, slope, base, ray, a0, a1, a2, wb);
+    } else if (xmajor) {
       if (any45)
         forward_walk<true, true, COUNT>(lo, hi, n, pk_yx, vg.sx, vg.sy, slope, base, ray, a0, a1, a2);
       else

@@ -99,6 +99,8 @@ __device__ __forceinline__ bool xcd_item(int nitems, int &item) {
 // of the same kernel (the memory is read-only for the kernel's lifetime:
 // tables, descriptors, work lists).
 #define OSSCIR_CONST __attribute__((address_space(4)))
+// Pointers into LDS (the destination of global-to-LDS loads).
+#define OSSCIR_LDS __attribute__((address_space(3)))
 
 template <typename T>
 __device__ __forceinline__ const OSSCIR_CONST T *as_const(const T *p) {

@@ -24,6 +24,10 @@ __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ f, int n
   pack_block(f, n, nch, pk_xy, pk_yx, blockIdx.x * 32, blockIdx.y * 32, tile);  // padded coordinates
 }
 
+// Rays per forward-projection workgroup (a chunk of consecutive bins of one
+// view); two waves per workgroup measured faster than one or four.
+constexpr int kFpBlock = 128;
+
 template <bool COUNT>
 __global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__restrict__ pk_xy,
                                                   const float4 *__restrict__ pk_yx, float *__restrict__ p,
@@ -33,7 +37,9 @@ __global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__re
   int item;
   if (!xcd_item(sd.n_views * nchunk, item)) return;
   const int v = item / nchunk;
-  forward_rays<COUNT>(sd, pk_xy, pk_yx, p, p_stride, nch, v, (item - v * nchunk) * bs);
+  __shared__ float4 fwd_lds[kFpBlock / 64][kFpUnroll * 64];  // 4 KB of image rows per wave
+  forward_rays<COUNT>(sd, pk_xy, pk_yx, p, p_stride, nch, v, (item - v * nchunk) * bs,
+                      (float4 OSSCIR_LDS *)fwd_lds[threadIdx.x >> 6]);
 }
 
 // ----------------------------------------------------------------- back
@@ -60,10 +66,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
 }
 
 // ----------------------------------------------------------------- launchers
-
-// Rays per forward-projection workgroup (a chunk of consecutive bins of one
-// view); two waves per workgroup measured faster than one or four.
-constexpr int kFpBlock = 128;
 
 static unsigned forward_blocks(const ScanDesc &sd) {
   const int items = sd.n_views * ((sd.n_bins + kFpBlock - 1) / kFpBlock);
