@@ -55,6 +55,8 @@ __global__ void __launch_bounds__(256, 6) kb_forward(const SlotDesc *__restrict_
   const int stride = gridDim.x / kXcds;
   const int cnt = list_count(wl, x);
   const int R = blockDim.x;
+  extern __shared__ float4 fwd_rows[];  // kFpUnroll x 64 image rows per wave (forward_walk_lds)
+  float4 OSSCIR_LDS *wb = (float4 OSSCIR_LDS *)(fwd_rows + (threadIdx.x >> 6) * (kFpUnroll * 64));
   for (int j = blockIdx.x / kXcds; j < cnt; j += stride) {
     const int it = list_item(wl, x, j);
     const int s = it >> kItemSlotShift, local = it & kItemLocalMask;
@@ -62,7 +64,7 @@ __global__ void __launch_bounds__(256, 6) kb_forward(const SlotDesc *__restrict_
     const SlotDesc sl = load_slot(slots, s);
     const int nchunk = (sl.sd.n_bins + R - 1) / R;
     const int v = local / nchunk;
-    forward_rays<false>(sl.sd, sl.pk_xy, sl.pk_yx, sl.p, sl.sd.n_rays, 3, v, (local - v * nchunk) * R);
+    forward_rays<false>(sl.sd, sl.pk_xy, sl.pk_yx, sl.p, sl.sd.n_rays, 3, v, (local - v * nchunk) * R, wb);
   }
 }
 
@@ -144,7 +146,8 @@ __global__ void __launch_bounds__(64) kb_tick(const SlotDesc *__restrict__ slots
 
 hipError_t launch_batch_forward(const SlotDesc *slots, const SlotStatus *status, WorkList wl, int rays_per_wg,
                                 hipStream_t st) {
-  hipLaunchKernelGGL(kb_forward, dim3((unsigned)wl.wgs), dim3((unsigned)rays_per_wg), 0, st, slots, status, wl);
+  const size_t lds = (size_t)(rays_per_wg / 64) * kFpUnroll * 64 * sizeof(float4);
+  hipLaunchKernelGGL(kb_forward, dim3((unsigned)wl.wgs), dim3((unsigned)rays_per_wg), lds, st, slots, status, wl);
   return hipGetLastError();
 }
 
