@@ -42,7 +42,7 @@ namespace osscir {
 constexpr int kBpTile = 16;
 constexpr int kBpThreads = kBpTile * kBpTile;
 constexpr int kBpMaxBins = 128;   // bins staged per view; wider shadows take a chunked path
-constexpr int kBpViewChunk = kBpThreads;
+constexpr int kBpViewChunk = 128;  // views whose tile bounds are computed together
 constexpr int kBpFlush = 8;       // views summed in FP32 before the FP64 running sum
 constexpr int kBpGroup = 4;       // views staged together (one wave each) in the common path
 constexpr int kBpSlot = 64;       // staged bins per view of a group (one lane each)
@@ -67,10 +67,23 @@ struct ViewTile {
   int pad0, pad1;
 };
 
+// Grouped staging of the fused primal path, filled by global-to-LDS copies
+// (16 bytes per lane, lane i at slot i): one array per 16-byte piece of a
+// bin: the ray table's (kappa nx, kappa ny) and the three pieces of qS
+// (q0..q3, q4..q7, and q8 with the ray's kappa a and hmax, written there by
+// the spectral kernel).
+struct BpSoa {
+  double2 a[kBpGroup][kBpSlot];  // kappa nx, kappa ny
+  float4 b[kBpGroup][kBpSlot];   // q0..q3
+  float4 c[kBpGroup][kBpSlot];   // q4..q7
+  float4 d[kBpGroup][kBpSlot];   // q8, kappa a, hmax, 0
+};
+
 struct BpShared {
   union {
     BinLDS bins[2][kBpMaxBins];          // per-view staging (wide shadows)
-    BinLDS gbins[kBpGroup][kBpSlot];     // grouped staging (common path)
+    BinLDS gbins[kBpGroup][kBpSlot];     // grouped staging (common path, planar q)
+    BpSoa soa[2];                        // grouped staging (fused primal path), double-buffered
     float4 tile[kBpTile][kBpTile + 1];  // epilogues, after the last view
   };
   ViewTile vt[kBpViewChunk];
@@ -444,12 +457,127 @@ __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int 
   __syncthreads();  // every wave is done with the staging slots, which epilogues reuse
 }
 
+// Global-to-LDS copies of one view's bins for the fused primal path (qS with
+// 12 floats per ray): wave su stages view j of the chunk into dst, lane sl
+// bin d0 + sl; lanes without a bin copy the plan's zero record.
+__device__ __forceinline__ void copy_group_view(const ScanDesc &sd, const float *__restrict__ qS, unsigned nb,
+                                                const BpShared &sh, int vc, int j, int cnt, int su, int sl,
+                                                BpSoa &dst) {
+  const ViewTile vt = sh.vt[min(j, cnt - 1)];
+  const bool has = j < cnt && sl < min(vt.nst, kBpSlot);
+  const unsigned l = (unsigned)(vc + j) * nb + (unsigned)(vt.d0 + sl);  // used only if has
+  const float4 *ra = has ? reinterpret_cast<const float4 *>(sd.rays + l) : sd.zero;
+  const float4 *qa = has ? reinterpret_cast<const float4 *>(qS) + 3 * (size_t)l : sd.zero;
+  __builtin_amdgcn_global_load_lds(ra, (void OSSCIR_LDS *)&dst.a[su][0], 16, 0, 0);
+  __builtin_amdgcn_global_load_lds(qa, (void OSSCIR_LDS *)&dst.b[su][0], 16, 0, 0);
+  __builtin_amdgcn_global_load_lds(qa + 1, (void OSSCIR_LDS *)&dst.c[su][0], 16, 0, 0);
+  __builtin_amdgcn_global_load_lds(qa + 2, (void OSSCIR_LDS *)&dst.d[su][0], 16, 0, 0);
+}
+
+template <int NCH>
+__device__ __forceinline__ void load_soa(const BpSoa &S, int u, int idx, BinLDS &e) {
+  e.n = S.a[u][idx];
+  const float4 d = S.d[u][idx];
+  e.w0 = make_float4(d.y, d.z, d.w, d.x);  // kappa a, hmax, 0, q8: the record accumulate_bin reads
+  e.w1 = S.b[u][idx];
+  if (NCH > 4) e.w2 = S.c[u][idx];
+}
+
+// The common path of the fused primal step: as back_accumulate_grouped, with
+// the next group's bins copied straight into the other LDS buffer while the
+// current group is summed (one barrier per group).  Same records, windows
+// and summation order, so the same bits.
+template <int NCH>
+__device__ __forceinline__ void back_accumulate_grouped_lds(const ScanDesc &sd, int tile_x, int tile_y,
+                                                            const float *__restrict__ qS, double acc[NCH],
+                                                            BpShared &sh) {
+  const int tid = threadIdx.x;
+  int tx, ty;
+  bp_pixel_of_thread(tid, tx, ty);
+  const int ix = tile_x * kBpTile + tx;
+  const int iy = tile_y * kBpTile + ty;
+  const int V = sd.n_views;
+  const unsigned nb = (unsigned)sd.n_bins;
+  const float X = (float)ix - sd.c0;
+  const float Y = (float)iy - sd.c0;
+  const float sid = in_vgpr(sd.sid_px);
+  const double fx = (double)ix, fy = (double)iy;
+  const int su = tid >> 6, sl = tid & 63;
+  static_assert(kBpGroup * 64 == kBpThreads && kBpSlot == 64, "one wave per view, one lane per bin");
+  static_assert(kBpViewChunk % kBpFlush == 0 && kBpFlush % kBpGroup == 0, "flushes at group ends");
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
+  for (int vc = 0; vc < V; vc += kBpViewChunk) {
+    const int cnt = min(kBpViewChunk, V - vc);
+    __syncthreads();  // the previous chunk is done with sh
+    if (tid < cnt) tile_view_bounds(sd, sd.views[vc + tid], tile_x, tile_y, sh.vt[tid]);
+    __syncthreads();
+    copy_group_view(sd, qS, nb, sh, vc, su, cnt, su, sl, sh.soa[0]);
+    float part[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) part[c] = 0.0f;
+    int buf = 0;
+    for (int g0 = 0; g0 < cnt; g0 += kBpGroup) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of the group have landed
+      __syncthreads();                // every wave's have; the other buffer's reads are done
+      if (g0 + kBpGroup < cnt) copy_group_view(sd, qS, nb, sh, vc, g0 + kBpGroup + su, cnt, su, sl, sh.soa[buf ^ 1]);
+      const BpSoa &S = sh.soa[buf];
+      ViewTile vt[kBpGroup];
+      ViewGeom vg[kBpGroup];
+#pragma unroll
+      for (int u = 0; u < kBpGroup; ++u) {
+        const int j = min(g0 + u, cnt - 1);
+        vt[u] = sh.vt[j];
+        vg[u] = load_uniform(sd.views + vc + j);
+      }
+      float t[kBpGroup];
+      int nst[kBpGroup], s[kBpGroup];
+      double dx[kBpGroup], dy[kBpGroup];
+      int kmax = 0;
+#pragma unroll
+      for (int u = 0; u < kBpGroup; ++u) {
+        nst[u] = g0 + u < cnt ? min(__builtin_amdgcn_readfirstlane(vt[u].nst), kBpSlot) : 0;
+        kmax = max(kmax, min(__builtin_amdgcn_readfirstlane(vt[u].K), nst[u]));
+        const float num = __fmaf_rn(vg[u].cb, Y, -vg[u].sb * X);
+        const float den = __fmaf_rn(-vg[u].sb, Y, __fmaf_rn(-vg[u].cb, X, sid));
+        t[u] = __fmaf_rn(num * __builtin_amdgcn_rcpf(den), sd.bin_scale, vt[u].off);
+        dx[u] = vg[u].sx - fx;
+        dy[u] = vg[u].sy - fy;
+      }
+#pragma unroll
+      for (int u = 0; u < kBpGroup; ++u) s[u] = clamp_0_hi(floor_to_int(t[u]), max(0, nst[u] - kmax));
+      const int kmx = __builtin_amdgcn_readfirstlane(kmax);
+      for (int i = 0; i < kmx; ++i) {
+#pragma unroll
+        for (int u = 0; u < kBpGroup; u += 2) {
+          BinLDS e0, e1;
+          load_soa<NCH>(S, u, s[u] + i, e0);
+          load_soa<NCH>(S, u + 1, s[u + 1] + i, e1);
+          accumulate_bin<NCH>(e0, dx[u], dy[u], part);
+          accumulate_bin<NCH>(e1, dx[u + 1], dy[u + 1], part);
+        }
+      }
+      if ((g0 + kBpGroup) % kBpFlush == 0 || g0 + kBpGroup >= cnt) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          acc[c] += (double)part[c];
+          part[c] = 0.0f;
+        }
+      }
+      buf ^= 1;
+    }
+  }
+  __syncthreads();  // every wave is done with the staging buffers, which epilogues reuse
+}
+
 template <int NCH, bool WIDE, bool QS12 = false>
 __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, int tile_y, const float *__restrict__ q,
                                                 int q_stride_i, double acc[NCH], BpShared &sh) {
   static_assert(NCH >= 1 && NCH <= 9, "1..9 channels");
   if (WIDE)
     back_accumulate_views<NCH, QS12>(sd, tile_x, tile_y, q, q_stride_i, acc, sh);
+  else if (QS12)
+    back_accumulate_grouped_lds<NCH>(sd, tile_x, tile_y, q, acc, sh);
   else
     back_accumulate_grouped<NCH, QS12>(sd, tile_x, tile_y, q, q_stride_i, acc, sh);
 }

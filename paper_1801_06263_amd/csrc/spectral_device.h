@@ -426,7 +426,8 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
     for (int w = 0; w < kWin; ++w) yw[w] = yw[w] + ss[w] * z[w];
   }
   // outputs: y, q = G^T y, and S (block) or h (diag), the latter two
-  // interleaved per ray as 12 floats (q0..2, S0..5 or h0..2, zero padding)
+  // interleaved per ray as 12 floats (q0..2, S0..5 or h0..2 and zeros up to
+  // q8, then the ray's kappa a, hmax and a zero)
 #pragma unroll
   for (int w = 0; w < kWin; ++w) y[w * L + l] = (float)yw[w];
   float o[12];
@@ -435,9 +436,12 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
     o[m] = (float)(a[0][m] * yw[0] + a[1][m] * yw[1] + a[2][m] * yw[2] + a[3][m] * yw[3]);
 #pragma unroll
   for (int j = 0; j < 9; ++j) o[3 + j] = (BLOCK ? j < 6 : j < 3) ? (float)extra[j < 6 ? j : 0] : 0.0f;
+  // the last piece also carries the ray's kappa a and hmax, so that the
+  // back-projector stages a bin as four 16-byte copies
+  const float4 rk = reinterpret_cast<const float4 *>(sd.rays + l)[1];  // kappa a, hmax, kappa, pad
   qs4[0] = make_float4(o[0], o[1], o[2], o[3]);
   qs4[1] = make_float4(o[4], o[5], o[6], o[7]);
-  qs4[2] = make_float4(o[8], o[9], o[10], o[11]);
+  qs4[2] = make_float4(o[8], rk.x, rk.y, 0.0f);
 }
 
 // ---------------------------------------------------------------- primal
