@@ -281,6 +281,15 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
         }
     }
   }
+  // global-to-LDS staging in the fused back-projection when the tiles fill
+  // four workgroups per CU (measured: 4% faster at 1024 tiles on 256 CUs,
+  // 8-10% slower at 256 tiles and fewer)
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1) cus = 256;
+    const int nt = (N + kBpTile - 1) / kBpTile;
+    sd.bp_copy = nt * nt >= 4 * cus ? 1 : 0;
+  }
   sd.rays = p->d_rays;
   sd.views = p->d_views;
   sd.rho = p->d_rho;

@@ -66,6 +66,7 @@ struct ScanDesc {
   float cbin;        // (n_bins - 1) / 2
   float n0[kWin];    // incident counts per window
   int bp_wide;       // some 16x16-tile shadow exceeds the back-projector's staging buffer
+  int bp_copy;       // enough tiles for four workgroups per CU: the fused step stages by global-to-LDS copies
   int per_bin;       // window responses and incident counts per detector bin
   int mfma;          // energy sums on the matrix cores (shared table, fits LDS)
   const float4 *sbin;   // [I][D] s_{w,d,i} (w = x, y, z, w), per_bin only

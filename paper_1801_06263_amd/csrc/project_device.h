@@ -570,13 +570,18 @@ __device__ __forceinline__ void back_accumulate_grouped_lds(const ScanDesc &sd, 
   __syncthreads();  // every wave is done with the staging buffers, which epilogues reuse
 }
 
-template <int NCH, bool WIDE, bool QS12 = false>
+// COPY (QS12 only): the grouped path stages by global-to-LDS copies.  Both
+// grouped variants give the same bits; the copies pay off when four
+// workgroups share a CU (the next group's copies then overlap other
+// workgroups' sums), register staging when the grid is small.
+template <int NCH, bool WIDE, bool QS12 = false, bool COPY = false>
 __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, int tile_y, const float *__restrict__ q,
                                                 int q_stride_i, double acc[NCH], BpShared &sh) {
   static_assert(NCH >= 1 && NCH <= 9, "1..9 channels");
+  static_assert(QS12 || !COPY, "global-to-LDS staging reads qS");
   if (WIDE)
     back_accumulate_views<NCH, QS12>(sd, tile_x, tile_y, q, q_stride_i, acc, sh);
-  else if (QS12)
+  else if (COPY)
     back_accumulate_grouped_lds<NCH>(sd, tile_x, tile_y, q, acc, sh);
   else
     back_accumulate_grouped<NCH, QS12>(sd, tile_x, tile_y, q, q_stride_i, acc, sh);

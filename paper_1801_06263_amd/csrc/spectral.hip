@@ -131,7 +131,7 @@ __global__ void k_scale_steps(int count, float lambda, float *__restrict__ v) {
 
 // PACK: fbar' is also written into the packed images of the next forward
 // projection (pk_xy, pk_yx: interior pixels; borders already zero)
-template <bool BLOCK, bool WIDE, bool PACK>
+template <bool BLOCK, bool WIDE, bool PACK, bool COPY>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_back_primal(ScanDesc sd, const float *__restrict__ qS,
                                                       float *__restrict__ f, float *__restrict__ fbar, float lambda,
                                                       float4 *__restrict__ pk_xy, float4 *__restrict__ pk_yx) {
@@ -141,8 +141,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
   if (!xcd_item(nt * nt, item)) return;
   const int t = as_const(sd.tile_order)[item];
   const int tile_y = t / nt;
-  back_primal_tile<BLOCK, WIDE, PACK>(sd, qS, f, fbar, lambda, t - tile_y * nt, tile_y, sh,
-                                      PrimalEpilogue{pk_xy, pk_yx, nullptr});
+  back_primal_tile<BLOCK, WIDE, PACK, COPY>(sd, qS, f, fbar, lambda, t - tile_y * nt, tile_y, sh,
+                                            PrimalEpilogue{pk_xy, pk_yx, nullptr});
 }
 
 // ---------------------------------------------------------------- D_TPL
@@ -261,20 +261,22 @@ hipError_t launch_back_primal(const ScanDesc &sd, const float *qS, float *f, flo
   const size_t np = (size_t)sd.n + 2 * kPad;
   float4 *pk_xy = reinterpret_cast<float4 *>(pack);
   float4 *pk_yx = pack ? pk_xy + np * np : nullptr;
-#define OSSCIR_BP(B, W, P)                                                                                   \
-  hipLaunchKernelGGL((k_back_primal<B, W, P>), pix_grid(sd), dim3(256), 0, st, sd, qS, f, fbar, lambda, pk_xy, \
+#define OSSCIR_BP(B, W, P, C)                                                                                   \
+  hipLaunchKernelGGL((k_back_primal<B, W, P, C>), pix_grid(sd), dim3(256), 0, st, sd, qS, f, fbar, lambda, pk_xy, \
                      pk_yx)
-#define OSSCIR_BP2(B, W) \
-  do {                   \
-    if (pack)            \
-      OSSCIR_BP(B, W, true); \
-    else                 \
-      OSSCIR_BP(B, W, false); \
+#define OSSCIR_BP2(B, P)                           \
+  do {                                             \
+    if (sd.bp_wide)                                \
+      OSSCIR_BP(B, true, P, false);                \
+    else if (sd.bp_copy)                           \
+      OSSCIR_BP(B, false, P, true);                \
+    else                                           \
+      OSSCIR_BP(B, false, P, false);               \
   } while (0)
   if (block) {
-    if (sd.bp_wide) OSSCIR_BP2(true, true); else OSSCIR_BP2(true, false);
+    if (pack) OSSCIR_BP2(true, true); else OSSCIR_BP2(true, false);
   } else {
-    if (sd.bp_wide) OSSCIR_BP2(false, true); else OSSCIR_BP2(false, false);
+    if (pack) OSSCIR_BP2(false, true); else OSSCIR_BP2(false, false);
   }
 #undef OSSCIR_BP2
 #undef OSSCIR_BP

@@ -462,13 +462,13 @@ struct PrimalEpilogue {
   double2 *partial;  // this tile's (sum |f' - f|^2, sum |f'|^2), or null
 };
 
-template <bool BLOCK, bool WIDE, bool EPI>
+template <bool BLOCK, bool WIDE, bool EPI, bool COPY>
 __device__ __forceinline__ void back_primal_tile(const ScanDesc &sd, const float *__restrict__ qS,
                                                  float *__restrict__ f, float *__restrict__ fbar, float lambda,
                                                  int tile_x, int tile_y, BpShared &sh, const PrimalEpilogue &epi) {
   constexpr int NCH = BLOCK ? 9 : 6;
   double acc[NCH];
-  back_accumulate<NCH, WIDE, true>(sd, tile_x, tile_y, qS, 0, acc, sh);
+  back_accumulate<NCH, WIDE, true, COPY>(sd, tile_x, tile_y, qS, 0, acc, sh);
   int tx, ty;
   bp_pixel_of_thread(threadIdx.x, tx, ty);
   const int ix = tile_x * kBpTile + tx;
