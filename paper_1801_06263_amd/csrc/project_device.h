@@ -13,7 +13,10 @@
 // one bin per lane, up to 64); slots past a view's shadow hold a null record
 // whose weight is exactly 0.  The loads of the next group are issued before
 // the current group is processed and stored after it, so a group costs two
-// barriers.  A pixel's non-zero weights in a view lie on the bins strictly
+// barriers.  With qS as input (the fused primal step) and a grid of at least
+// four workgroups per CU, the bins are instead copied straight from memory
+// into double-buffered LDS arrays (global-to-LDS loads, one barrier per
+// group); both stagings hold the same records.  A pixel's non-zero weights in a view lie on the bins strictly
 // inside (tau - hw, tau + hw), tau being its centre's detector position: at
 // most K = floor(2 hw) + 1 consecutive bins.  Every thread reads, in each of
 // the group's views, a window of Kmax = max K of the group staged bins
