@@ -20,8 +20,11 @@ Modules
              point.
 
 Parity status of each function is stated in its docstring; every function is
-pinned by the ``-m "not gpu"`` tests except the iterate trajectory itself
-(no iterate values are printed in the paper): that is "parity unpinned" and
-only checked through invariants (fixed point, rotation equivariance,
-descent of D_TPL, the block-vs-diagonal claim).
+pinned by the ``-m "not gpu"`` tests.  The paper prints no iterate values, so
+the MOCCA iteration is pinned through properties the mathematics fixes: the
+Fejer monotonicity and closed-form limit of the CPPD step on a fixed convex
+quadratic, equality with a dense CPPD step written from the definitions, the
+fixed point at the truth, rotation equivariance of block SPC and the
+block-vs-diagonal claim.  The expansion point fbar_n is a reading of the
+paper (it leaves it unstated).
 """

@@ -7,7 +7,7 @@ and step lengths recomputed from K(f0) every iteration (one inner iteration
 per expansion point, as in the paper's experiments).
 
 The paper defers the exact quadratic Q to its Ref. [Barber2016b]; the reading
-used here (see the design doc's list of readings) is, per ray l and with
+used here is, per ray l and with
 u = (K f)_l in R^W, u0 = (K(f0) f0)_l = G_l p_l(f0):
 
     Q_l(u) = r_l^T (u - u0) + 1/2 (u - u0)^T D_l (u - u0)
@@ -25,9 +25,17 @@ Rays that miss the image (rho_l = 0) have a zero row in K and are masked
 (y = 0).  No constraint on f is imposed (softexp removes the need), so the
 primal prox is the identity.
 
-Parity of the trajectory is unpinned (the paper prints no iterates); the
-tests pin it through the fixed point at the truth, rotation equivariance of
-block SPC, the monochromatic closed form and descent of D_TPL.
+The paper prints no iterates, so the trajectory is pinned through what the
+mathematics fixes: with the expansion point held fixed the step is plain CPPD
+on one convex quadratic, whose M-distance to the closed-form saddle point
+never increases and whose iterates converge to the closed-form minimiser
+(theta = 0 breaks it); one MOCCA step equals a dense CPPD step written from
+the definitions (explicit K = A Z, the paper's sums for Sigma and T^-1, the
+dual prox by a numerical minimiser); the truth is a fixed point on noiseless
+data; block SPC is rotation equivariant; the monochromatic case converges to
+Beer-Lambert's closed form; D_TPL descends.  The expansion point (fbar_n,
+which the paper leaves unstated) is a reading; the dense cross-check holds
+the oracle to it.
 """
 from __future__ import annotations
 
@@ -86,12 +94,31 @@ def initial_state(n_mat, n_pix, n_rays, n_win, f0=None) -> State:
 
 
 def mocca_step(X, rho, state: State, c, spec, lam: float, precond: str = "block",
-               curvature: str = "clip", parts: Optional[dict] = None) -> State:
-    """One MOCCA iteration; ``parts`` (if a dict) receives the intermediates."""
+               curvature: str = "clip", parts: Optional[dict] = None, theta: float = 1.0,
+               expansion=None) -> State:
+    """One CPPD step on the local convex quadratic of L_TPL (Sec. I, Sec. II):
+
+        y_{n+1}    = prox_{Sigma Q*}(y_n + Sigma K(f0) fbar_n)
+        f_{n+1}    = f_n - T K(f0)^T y_{n+1}
+        fbar_{n+1} = f_{n+1} + theta (f_{n+1} - f_n)
+
+    with K, Sigma, T and the quadratic Q (its r, D and u0 = K(f0) f0) formed
+    at the expansion point f0.  MOCCA, one inner iteration per expansion
+    point, is expansion=None (f0 = fbar_n) and theta = 1.  ``expansion`` may
+    also be "current" (f0 = f_n) or a fixed [M, P] array, which turns the
+    step into plain CPPD on one fixed convex quadratic.  ``parts`` (if a
+    dict) receives the intermediates."""
     M = spec.n_mat
     mask = rho > 0
-    # expansion point f0 = fbar_n
-    p = X @ state.fbar.T                                  # [L, M]
+    pbar = X @ state.fbar.T                               # [L, M]
+    if expansion is None:
+        p = pbar
+    elif isinstance(expansion, str):
+        if expansion != "current":
+            raise ValueError(expansion)
+        p = X @ state.f.T
+    else:
+        p = X @ np.asarray(expansion, dtype=np.float64).reshape(M, -1).T
     A, B, g = model.matrices_AB(p, spec)
     chat = model.incident(spec) * g                       # Eq. (finalModel)
     r = model.residual(c, chat)
@@ -110,11 +137,12 @@ def mocca_step(X, rho, state: State, c, spec, lam: float, precond: str = "block"
         sigma, tau = spc.diag_steps_factored(G, X, rho, lam)
     else:
         raise ValueError(precond)
-    # dual step y_{n+1} = prox_{Sigma Q*}(y_n + Sigma K fbar_n)
+    # dual step y_{n+1} = prox_{Sigma Q*}(y_n + Sigma K(f0) fbar_n), u0 = K(f0) f0
     u0 = np.einsum("lwm,lm->lw", G, p)
+    kfbar = u0 if expansion is None else np.einsum("lwm,lm->lw", G, pbar)
     y_new = np.zeros_like(state.y)
     sig_m = sigma[mask]
-    y_new[mask] = dual_prox(state.y[mask] + sig_m * u0[mask], u0[mask], sig_m, r[mask], D[mask])
+    y_new[mask] = dual_prox(state.y[mask] + sig_m * kfbar[mask], u0[mask], sig_m, r[mask], D[mask])
     # primal step f_{n+1} = f_n - T K^T y_{n+1}
     q = np.einsum("lwm,lw->lm", G, y_new)                 # G_l^T y_l
     b = (X.T @ q).T                                       # K^T y, [M, P]
@@ -122,7 +150,7 @@ def mocca_step(X, rho, state: State, c, spec, lam: float, precond: str = "block"
         f_new = state.f - np.linalg.solve(tinv, b.T[..., None])[..., 0].T
     else:
         f_new = state.f - tau.T * b
-    fbar_new = 2.0 * f_new - state.f
+    fbar_new = f_new + theta * (f_new - state.f)
     if parts is not None:
         parts.update(p=p, chat=chat, r=r, G=G, H=H, D=D, sigma=sigma, u0=u0, y=y_new, q=q, b=b,
                      f=f_new, fbar=fbar_new)

@@ -373,6 +373,207 @@ def test_claim_block_spc_beats_diagonal_spc(micro):
     assert best["block"] < 0.1 * best["diag"]
 
 
+# ------------------------------------------------------------ CPPD composition
+#
+# With the expansion point held fixed, a MOCCA step is plain CPPD (dual prox,
+# primal step, extrapolation) on one fixed convex quadratic problem
+# min_f Q(K f).  Written with pairs w_n = (f_{n-1}, y_n), that iteration is a
+# proximal point method in the metric M = [[T^-1, -K^T], [-K, Sigma^-1]]
+# (He and Yuan's reading of Chambolle-Pock), so for theta = 1 and M PSD the
+# M-distance to any saddle point (f*, y*) never increases, and the iterates
+# converge to the minimiser, which here has a closed form.  A dropped
+# extrapolation (theta = 0, the Arrow-Hurwicz step) breaks the monotonicity.
+
+def _composition_problem(n=8, views=12, bins=16, seed=3):
+    geom = synth.make_geometry(n, 20.0, views, bins)
+    spec = synth.make_spectral(20, 119, 120.0, 1e5, e_step=5)
+    f_true = synth.inserts_phantom(n, 20.0)
+    X = pj.system_matrix(geom)
+    rho = np.asarray(X.sum(axis=1)).ravel()
+    c = synth.poisson_counts(model.counts_model(X @ f_true.reshape(3, -1).T, spec), seed)
+    rng = np.random.default_rng(seed)
+    f0 = f_true.reshape(3, -1) * (1.0 + 0.2 * rng.standard_normal((3, n * n)))
+    return spec, X, rho, c, f0
+
+
+def _dense_K_from_AZ(A, mu, Xd):
+    """K = A(f) Z of Sec. II as dense matrices: A [(w,l), (l',i)] is
+    block-diagonal over rays, Z [(l,i), (m,k)] = mu_{m,i} X_{l,k}; rows
+    w-major (w L + l), columns m-major (m P + k)."""
+    L, W, I = A.shape
+    M, P = mu.shape[0], Xd.shape[1]
+    Ad = np.zeros((W, L, L, I))
+    Ad[:, np.arange(L), np.arange(L), :] = A.transpose(1, 0, 2)
+    Z = np.einsum("mi,lk->limk", mu, Xd).reshape(L * I, M * P)
+    return Ad.reshape(W * L, L * I) @ Z
+
+
+def _block_rows(D):
+    """Per-ray W x W blocks [L, W, W] -> dense matrix in (w, l) row order."""
+    L, W, _ = D.shape
+    out = np.zeros((W * L, W * L))
+    for l in range(L):
+        idx = np.arange(W) * L + l
+        out[np.ix_(idx, idx)] = D[l]
+    return out
+
+
+def _fixed_quadratic(spec, X, rho, c, f0, lam, precond, curv):
+    """Dense K(f0), the curvature and linear term of Q, the closed-form
+    minimiser f* of Q(K f) with its dual y* = grad Q(K f*), and M."""
+    p0 = X @ f0.T
+    A, B, g = model.matrices_AB(p0, spec)
+    chat = model.incident(spec) * g
+    r = model.residual(c, chat)
+    G = model.ray_jacobian_from_A(A, spec)
+    D = mocca.curvature_clip(G, model.hessian_from_AB(A, B, g, c, spec)) if curv == "clip" \
+        else mocca.curvature_window(c)
+    K = _dense_K_from_AZ(A, spec.mu, X.toarray())
+    Dd = _block_rows(D)
+    rr, uu = r.T.ravel(), (K @ f0.ravel())
+    fs = np.linalg.solve(K.T @ Dd @ K, K.T @ (Dd @ uu - rr))
+    ys = rr + Dd @ (K @ fs - uu)
+    hit = np.tile(rho > 0, spec.n_win)
+    ys[~hit] = 0.0
+    if precond == "block":
+        sinv, tinv = spc.block_steps_dense(K, lam, spec.n_mat)
+        Mm = spc.assemble_M(K, tinv_blocks=tinv, sigma_inv=sinv)
+    else:
+        sigma, tau = spc.diag_steps_dense(K, lam, spec.n_mat)
+        Mm = spc.assemble_M(K, tau=tau, sigma_inv=np.where(sigma > 0, 1.0 / np.where(sigma > 0, sigma, 1.0), 0.0))
+    return K, fs, ys, Mm
+
+
+def _frozen_run(spec, X, rho, c, f0, lam, precond, curv, n_it, theta, fs, ys, Mm):
+    """M-distances |w_n - w*|_M^2 of the frozen-expansion iteration, w_n = (f_{n-1}, y_n)."""
+    st = mocca.initial_state(3, X.shape[1], X.shape[0], spec.n_win)
+    prev = st.f.copy()
+    wstar = np.concatenate([fs, ys])
+    dist = []
+    for _ in range(n_it):
+        w = np.concatenate([prev.ravel(), st.y.T.ravel()]) - wstar
+        dist.append(w @ Mm @ w)
+        prev = st.f.copy()
+        st = mocca.mocca_step(X, rho, st, c, spec, lam, precond, curv, theta=theta, expansion=f0)
+    return np.array(dist), st
+
+
+@pytest.fixture(scope="module")
+def composition():
+    return _composition_problem()
+
+
+@pytest.mark.parametrize("precond,curv,n_it", [("block", "window", 2000), ("block", "clip", 300),
+                                                ("diag", "window", 300)])
+def test_frozen_expansion_cppd_fejer_monotone(composition, precond, curv, n_it):
+    spec, X, rho, c, f0 = composition
+    lam = 1e-5
+    K, fs, ys, Mm = _fixed_quadratic(spec, X, rho, c, f0, lam, precond, curv)
+    # (f*, y*) is a saddle point: K^T y* = 0 and y* = grad Q(K f*)
+    assert np.abs(K.T @ ys).max() <= 1e-9 * np.abs(ys).max() * np.abs(K).max()
+    ev = np.linalg.eigvalsh(Mm)
+    assert ev.min() >= -1e-12 * ev.max()
+    dist, st = _frozen_run(spec, X, rho, c, f0, lam, precond, curv, n_it, 1.0, fs, ys, Mm)
+    assert (np.diff(dist) <= 1e-10 * dist[:-1]).all()
+    assert dist[-1] < 0.5 * dist[0]
+    if n_it >= 2000:
+        # converged to the closed-form minimiser of Q(K f)
+        assert np.linalg.norm(st.f.ravel() - fs) <= 1e-5 * np.linalg.norm(fs)
+        assert np.linalg.norm(st.y.T.ravel() - ys) <= 1e-3 * np.linalg.norm(ys)
+
+
+@pytest.mark.parametrize("curv", ["window", "clip"])
+def test_planted_no_extrapolation_breaks_fejer(composition, curv):
+    # planted mistake in the oracle step: theta = 0 instead of 1
+    spec, X, rho, c, f0 = composition
+    lam = 1e-5
+    _, fs, ys, Mm = _fixed_quadratic(spec, X, rho, c, f0, lam, "block", curv)
+    dist, _ = _frozen_run(spec, X, rho, c, f0, lam, "block", curv, 100, 0.0, fs, ys, Mm)
+    assert (np.diff(dist) > 1e-3 * dist[:-1]).any()
+
+
+def _generic_mocca_step(spec, X, rho, c, state, lam, curv):
+    """One MOCCA step from the definitions, dense: K(f0) = A(f0) Z at the
+    expansion point f0 = fbar_n, Sigma and T^-1 from the paper's sums over
+    K, the quadratic Q(u) = r.(u - u0) + 1/2 (u - u0)^T D (u - u0) with
+    u0 = K(f0) f0, the dual prox argmin_y Q*(y) + 1/2 |y - v|^2_{Sigma^-1}
+    at v = y_n + Sigma K fbar_n found by a numerical minimiser (through its
+    optimality condition y = grad Q(u), u = Sigma^-1 (v - y): u minimises
+    Q(u) + 1/2 u^T Sigma u - v.u), the primal step f - T K^T y with T the
+    inverse of the assembled block-diagonal T^-1, and fbar = 2 f' - f."""
+    from scipy.optimize import minimize
+    Xd = X.toarray()
+    f0 = state.fbar
+    A, B, g = model.matrices_AB(Xd @ f0.T, spec)
+    r = model.residual(c, model.incident(spec) * g)
+    G = model.ray_jacobian_from_A(A, spec)
+    D = mocca.curvature_clip(G, model.hessian_from_AB(A, B, g, c, spec)) if curv == "clip" \
+        else mocca.curvature_window(c)
+    K = _dense_K_from_AZ(A, spec.mu, Xd)
+    sinv, tinv = spc.block_steps_dense(K, lam, spec.n_mat)
+    L, W = state.y.shape
+    sinv_l = sinv.reshape(W, L).T                     # [L, W]
+    ray = sinv_l[:, 0] > 0                            # rays that meet the image
+    u0 = (K @ f0.ravel()).reshape(W, L).T
+    kfb = (K @ state.fbar.ravel()).reshape(W, L).T
+    y = np.zeros((L, W))
+    for l in np.flatnonzero(ray):
+        sig = 1.0 / sinv_l[l]
+        v = state.y[l] + sig * kfb[l]
+        Dl, rl, u0l = D[l], r[l], u0[l]
+
+        def phi(u):
+            d = u - u0l
+            return rl @ d + 0.5 * d @ Dl @ d + 0.5 * (sig * u) @ u - v @ u
+
+        res = minimize(phi, np.zeros(W), jac=lambda u: rl + Dl @ (u - u0l) + sig * u - v,
+                       hess=lambda u: Dl + np.diag(sig), method="trust-exact", options={"gtol": 1e-12 * np.abs(v).max()})
+        y[l] = v - sig * res.x
+    y = y.T.ravel()
+    P = Xd.shape[1]
+    Tinv = spc.assemble_M(np.zeros((0, 3 * P)), tinv_blocks=tinv, sigma_inv=np.zeros(0))
+    f = state.f.ravel() - np.linalg.solve(Tinv, K.T @ y)
+    fbar = 2.0 * f - state.f.ravel()
+    return f.reshape(3, -1), fbar.reshape(3, -1), y.reshape(W, L).T
+
+
+@pytest.mark.parametrize("curv", ["clip", "window"])
+def test_mocca_step_equals_dense_cppd_definition(composition, curv):
+    spec, X, rho, c, _ = composition
+    lam = 1e-5
+    st, _ = mocca.mocca(X, c, spec, lam, 3, "block", curv)   # a state with f != fbar and y != 0
+    assert np.abs(st.f - st.fbar).max() > 1e-3 * np.abs(st.f).max()
+    f_ref, fb_ref, y_ref = _generic_mocca_step(spec, X, rho, c, st, lam, curv)
+
+    def err(s):
+        return max(np.abs(s.f - f_ref).max() / np.abs(f_ref).max(),
+                   np.abs(s.fbar - fb_ref).max() / np.abs(fb_ref).max(),
+                   np.abs(s.y - y_ref).max() / np.abs(y_ref).max())
+
+    assert err(mocca.mocca_step(X, rho, st, c, spec, lam, "block", curv)) <= 1e-10
+    # planted mistakes in the oracle step: no extrapolation, expansion about f_n
+    assert err(mocca.mocca_step(X, rho, st, c, spec, lam, "block", curv, theta=0.0)) > 1e-4
+    assert err(mocca.mocca_step(X, rho, st, c, spec, lam, "block", curv, expansion="current")) > 1e-4
+
+
+def test_dtpl_is_poisson_deviance_including_zero_counts():
+    # Eq. (DTPL) is the Poisson log-likelihood ratio of the saturated model
+    # (mean = c) over the model mean chat, summed over windows and rays; a
+    # zero count contributes chat (0 log 0 = 0)
+    from scipy.stats import poisson
+    rng = np.random.default_rng(5)
+    chat = rng.uniform(0.05, 40.0, (300, 4))
+    c = rng.poisson(chat).astype(np.float64)
+    c[::5, 1] = 0.0
+    c[::3, 3] = 0.0
+    assert (c == 0).sum() > 100
+    ref = poisson.logpmf(c, c) - poisson.logpmf(c, chat)
+    terms = model.dtpl_terms(c, chat)
+    np.testing.assert_allclose(terms, ref, rtol=1e-10, atol=1e-12)
+    np.testing.assert_array_equal(terms[c == 0], chat[c == 0])
+    np.testing.assert_allclose(model.dtpl(c, chat), ref.sum(), rtol=1e-12)
+
+
 # ------------------------------------------------------------ mu-PC
 
 from oracle import mupc  # noqa: E402
