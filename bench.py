@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--fp64-small", type=int, default=1)
     ap.add_argument("--lam", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", default="24,72", help="view-subset sizes of the oracle sample")
+    ap.add_argument("--cpu-iters", type=int, default=3, help="whole oracle iterations timed for the CPU baseline")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--legs", default="single,batched,serving",
                     help="comma list of single (the 512^2 iteration rate), batched, serving, convergence; a run "
@@ -79,7 +79,9 @@ def parse():
                     help="iterations per slice of the batched leg (0 skips it)")
     ap.add_argument("--batch-per-size", type=int, default=6, help="slices per size in the batched mix")
     ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving leg (0 skips it)")
-    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrival rate of the serving leg (1/s)")
+    ap.add_argument("--serve-rates", default="4,64",
+                    help="comma list of Poisson arrival rates (1/s) of the serving leg: a light one and one that "
+                         "saturates the one-slot loop")
     ap.add_argument("--serve-tick", type=int, default=5, help="iterations between admissions and retirements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) to calibrate HBM byte counters")
@@ -124,38 +126,47 @@ def measured_traffic(kernel: str, workload: str):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(pr, lam, precond, curvature, view_counts):
-    """The FP64 oracle's MOCCA iteration timed on host cores over view subsets
-    of the same scan; the per-iteration time is extrapolated linearly in the
-    number of views (fixed per-pixel cost + per-ray cost)."""
+def host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pr, lam, precond, curvature, n_iter):
+    """The FP64 oracle's MOCCA iteration on the full scan, timed on one host
+    core: the system matrix X is built once (timed separately), then n_iter
+    whole iterations from f = 0 are timed."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import synth
     from oracle import model, mocca, projector
 
-    times = []
     with threadpool_limits(limits=1):
-        for nv in view_counts:
-            views = np.linspace(0, pr.geom.n_views, nv, endpoint=False).astype(int)
-            X = projector.system_matrix(pr.geom, views=views)
-            chat = model.counts_model(X @ pr.f_true.reshape(3, -1).T, pr.spec)
-            c = synth.poisson_counts(chat, pr.seed)
-            rho = np.asarray(X.sum(axis=1)).ravel()
-            st = mocca.initial_state(3, X.shape[1], X.shape[0], 4)
+        t0 = time.perf_counter()
+        X = projector.system_matrix(pr.geom)
+        t_build = time.perf_counter() - t0
+        chat = model.counts_model(X @ pr.f_true.reshape(3, -1).T, pr.spec)
+        c = synth.poisson_counts(chat, pr.seed)
+        rho = np.asarray(X.sum(axis=1)).ravel()
+        st = mocca.initial_state(3, X.shape[1], X.shape[0], 4)
+        t0 = time.perf_counter()
+        for _ in range(n_iter):
             st = mocca.mocca_step(X, rho, st, c, pr.spec, lam, precond, curvature)
-            t0 = time.perf_counter()
-            reps = 2
-            for _ in range(reps):
-                st = mocca.mocca_step(X, rho, st, c, pr.spec, lam, precond, curvature)
-            times.append((nv, (time.perf_counter() - t0) / reps))
-    (v0, t0), (v1, t1) = times[0], times[-1]
-    slope = (t1 - t0) / (v1 - v0)
-    t_full = t0 + slope * (pr.geom.n_views - v0)
-    sample = (f"{'+'.join(str(v) for v, _ in times)}-view subsets of the {pr.geom.n_views}-view scan, "
-              f"{'/'.join(f'{t:.2f}' for _, t in times)} s per iteration, linear in views -> "
-              f"{t_full:.1f} s per full iteration")
-    return {"value": 1.0 / t_full, "unit": "iter/s", "cores": 1, "kind": "oracle", "sample": sample}
+        t_iter = (time.perf_counter() - t0) / n_iter
+    nnz = X.nnz
+    del X
+    sample = (f"{n_iter} whole MOCCA iterations from f = 0 on the full {pr.geom.n}^2, {pr.geom.n_views} x "
+              f"{pr.geom.n_bins} scan ({pr.spec.n_energy} energies), {t_iter:.2f} s each; the CSR system matrix "
+              f"({nnz} nonzeros) built once beforehand in {t_build:.1f} s (not in the rate)")
+    return {"value": round(1.0 / t_iter, 5), "unit": "iter/s", "cores": 1, "kind": "oracle", "sample": sample,
+            "x_build_s": round(t_build, 1), "s_per_iteration": round(t_iter, 3), "host_cpu": host_cpu(),
+            "host_nproc": os.cpu_count()}
 
 
 def library_counts(plan, pr):
@@ -368,6 +379,16 @@ def serving_leg(n_requests: int, rate: float, per_tick: int, batch_cfg=None, see
     }
 
 
+def serving_rates(args, cfg):
+    """The serving leg at each arrival rate of --serve-rates (same requests
+    and arrival draws, scaled to the rate)."""
+    out = {}
+    for rate in [float(r) for r in args.serve_rates.split(",") if r]:
+        print(f"[bench] serving leg: {args.serve_requests} requests at {rate}/s", file=sys.stderr, flush=True)
+        out[f"{rate:g}_per_s"] = serving_leg(args.serve_requests, rate, args.serve_tick, cfg)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -392,7 +413,7 @@ def main():
             line["batched"] = batched_leg(args.batch_iters, args.batch_per_size)
         if "serving" in legs:
             cfg = line.get("batched", {}).get("tuned_config")
-            line["serving"] = serving_leg(args.serve_requests, args.serve_rate, args.serve_tick, cfg)
+            line["serving"] = serving_rates(args, cfg)
         if "convergence" in legs:
             line["convergence"] = convergence_leg(args.conv_workloads)
         print(json.dumps(line), flush=True)
@@ -525,14 +546,12 @@ def main():
         line["batched"] = batched_leg(args.batch_iters, args.batch_per_size)
         print(f"[bench] batched: {line['batched']}", file=sys.stderr, flush=True)
     if "serving" in legs and args.serve_requests > 0:
-        print(f"[bench] serving leg: {args.serve_requests} requests at {args.serve_rate}/s", file=sys.stderr,
-              flush=True)
         cfg = line.get("batched", {}).get("tuned_config")
-        line["serving"] = serving_leg(args.serve_requests, args.serve_rate, args.serve_tick, cfg)
+        line["serving"] = serving_rates(args, cfg)
     if not args.no_cpu_baseline:
-        views = [int(v) for v in args.cpu_views.split(",")]
-        print(f"[bench] cpu baseline: oracle on {views}-view subsets", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(pr, lam, args.precond, args.curvature, views)
+        print(f"[bench] cpu baseline: {args.cpu_iters} oracle iterations on the full scan", file=sys.stderr,
+              flush=True)
+        line["cpu_baseline"] = cpu_baseline(pr, lam, args.precond, args.curvature, args.cpu_iters)
     out = json.dumps(line)
     print(out, flush=True)
     if args.json_out:

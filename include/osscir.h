@@ -127,6 +127,18 @@ typedef struct {
 int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec, osscir_plan *out);
 int osscir_plan_destroy(osscir_plan plan);
 
+/* How the spectral step of an iteration forms its per-ray energy sums (the
+ * window sums, Jacobian rows and curvature sums over the energy bins of
+ * Eq. finalModel and the Hessian of Sec. II): matrix_cores = 1 runs them as a
+ * dense FP32 contraction of the response table with the softexp values of
+ * 64 rays on the matrix cores (the default wherever it applies: one shared
+ * response table within 64 KB of LDS, i.e. n_resp <= 1 and n_energy <= 336);
+ * 0 sums them per ray with vector FMAs in energy order.  Both are FP32 and
+ * meet the same bars against the FP64 oracle; their roundings differ.  Takes
+ * effect for the plan's later calls and for batch slots bound afterwards.
+ * EINVAL if matrix_cores = 1 where it does not apply. */
+int osscir_plan_set_energy_sums(osscir_plan plan, int32_t matrix_cores);
+
 /* Bytes of device scratch osscir_mocca_iterate, osscir_dtpl and the step
  * calls need (host out-parameter). */
 int osscir_workspace_bytes(osscir_plan plan, size_t *bytes);
@@ -134,6 +146,22 @@ int osscir_workspace_bytes(osscir_plan plan, size_t *bytes);
 /* rho_l = sum_k X_{l,k} (cm), the chord of each ray through the image square:
  * copies the plan's [L] array into rho (device). */
 int osscir_ray_lengths(osscir_plan plan, float *rho, osscir_stream stream);
+
+/* Host only, no device work: the per-view sources and per-ray line
+ * parameters a plan of this geometry evaluates X with (Sec. II, Eq. fullModel:
+ * X_{l,k} is the chord of ray l in pixel k).  In pixel index coordinates
+ * (pixel (ix, iy) centred at (ix, iy)) the chord is
+ *   clamp(kappa a - |kappa n . (S_v - (ix, iy))|, 0, hmax)   (cm)
+ * with n the ray's unit normal, a = (|n_x| + |n_y|) / 2, kappa =
+ * pixel_cm / |n_x n_y| and hmax = pixel_cm / max(|n_x|, |n_y|).  A ray
+ * within 2^-23 of an image axis (exactly parallel at views whose angle is a
+ * multiple of pi/2) is turned about its source to that tilt, toward the +
+ * side of its minor axis: a line lying exactly on a pixel edge is counted
+ * once, in the pixel on its + side.
+ * Outputs (HOST): rays [L][6] = kappa n_x, kappa n_y (the FP64 values the
+ * kernels use), kappa a, hmax, kappa (their FP32 values), 0; src [n_views][2]
+ * = the source (FP64).  EINVAL on a geometry osscir_plan_create rejects. */
+int osscir_ray_table(const osscir_geometry *geom, double *rays, double *src);
 
 /* Forward projection p_{c,l} = sum_k X_{l,k} f_{c,k} (Eq. fullModel's
  * X f) of n_ch >= 1 channels: f [n_ch][n][n] -> p [n_ch][V][D].  Ray-driven;

@@ -21,13 +21,23 @@ import numpy as np
 import scipy.sparse as sp
 
 
+def view_cos_sin(beta):
+    """cos and sin of the view angles, taken exactly (0 and +-1) where the
+    angle is a multiple of pi/2: the rays of such a view through the
+    detector centre are exactly parallel to an image axis, which FP64's
+    cos(pi/2) ~ 6e-17 would turn by rounding alone."""
+    cb, sb = np.cos(beta), np.sin(beta)
+    zc, zs = np.abs(cb) < 1e-12, np.abs(sb) < 1e-12
+    return np.where(zc, 0.0, np.where(zs, np.sign(cb), cb)), np.where(zs, 0.0, np.where(zc, np.sign(sb), sb))
+
+
 def ray_endpoints(geom, views: Optional[Sequence[int]] = None):
     """Source S and detector-bin centre P of every ray, shape [n_rays, 2] each.
 
     Rays are ordered view-major, bin-minor, over ``views`` (default: all)."""
     v = np.arange(geom.n_views) if views is None else np.asarray(views, dtype=np.int64)
     beta = geom.view0_rad + geom.arc_rad * v / geom.n_views
-    cb, sb = np.cos(beta), np.sin(beta)
+    cb, sb = view_cos_sin(beta)
     u = (np.arange(geom.n_bins) - (geom.n_bins - 1) / 2.0) * geom.bin_cm
     s = np.stack([geom.sid_cm * cb, geom.sid_cm * sb], axis=1)                      # [V,2]
     dc = np.stack([-(geom.sdd_cm - geom.sid_cm) * cb, -(geom.sdd_cm - geom.sid_cm) * sb], axis=1)
@@ -68,8 +78,10 @@ def _siddon_chunk(S, P, n, pix):
     mid = 0.5 * (allv[:, 1:] + allv[:, :-1])
     xm = S[:, :1] + mid * d[:, :1]
     ym = S[:, 1:] + mid * d[:, 1:]
-    ix = np.floor((xm + half) / pix).astype(np.int64)
-    iy = np.floor((ym + half) / pix).astype(np.int64)
+    # pixels are half-open, [edge_i, edge_i+1): a segment lying on a shared
+    # grid line (a ray exactly on an edge) belongs to the pixel on its + side
+    ix = np.floor(xm / pix + 0.5 * n).astype(np.int64)
+    iy = np.floor(ym / pix + 0.5 * n).astype(np.int64)
     keep = (seg > 0.0) & hit[:, None]
     r_idx = np.broadcast_to(np.arange(S.shape[0])[:, None], seg.shape)[keep]
     ix, iy = ix[keep], iy[keep]

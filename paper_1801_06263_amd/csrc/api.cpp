@@ -87,6 +87,86 @@ void free_plan(osscir_plan p) {
   delete p;
 }
 
+// cos and sin of a view angle, exact (0 and +-1) where the angle is a
+// multiple of pi/2: the detector-centre ray of such a view is parallel to an
+// image axis, which FP64's cos(pi/2) ~ 6e-17 would turn by rounding alone.
+void view_cos_sin(double beta, double &cb, double &sb) {
+  cb = std::cos(beta);
+  sb = std::sin(beta);
+  const bool zc = std::fabs(cb) < 1e-12, zs = std::fabs(sb) < 1e-12;
+  if (zc) cb = 0.0, sb = sb > 0 ? 1.0 : -1.0;
+  if (zs) sb = 0.0, cb = cb > 0 ? 1.0 : -1.0;
+}
+
+// Smallest |t_x t_y| of a ray direction the trapezoid weight is evaluated
+// with.  A ray closer to an image axis (exactly parallel at the cardinal
+// views) is turned about its source until its minor-axis component is
+// +kMinTilt: inside the image it then lies at most ~kMinTilt * 60 cm (well
+// under 1e-5 cm) to the + side of the exact line, so a line lying exactly on
+// a shared pixel edge is counted once, in the pixel on its + side (pixels
+// are half-open), and every weight stays exact with a finite trapezoid slope
+// kappa = h / |t_x t_y| <= 8.4e6 h, whose FP32 constants still resolve the
+// line's distance from each pixel edge.
+constexpr double kMinTilt = 1.0 / 8388608.0;  // 2^-23
+
+}  // namespace
+
+// Per-view source position and per-ray line parameters, in pixel index
+// coordinates (pixel (ix, iy) centred at (ix, iy)): normals scaled by kappa
+// in FP64, the trapezoid constants rounded to FP32.
+void osscir::build_ray_table(const osscir_geometry &g, std::vector<RayLine> &rays, std::vector<ViewGeom> &views) {
+  const int V = g.n_views, D = g.n_bins, N = g.n;
+  const double h = g.pixel_cm, c0 = 0.5 * (N - 1);
+  rays.resize((size_t)V * D);
+  views.resize(V);
+  for (int v = 0; v < V; ++v) {
+    double cb, sb;
+    view_cos_sin(g.view0_rad + g.arc_rad * (double)v / (double)V, cb, sb);
+    const double sx = g.sid_cm * cb / h + c0, sy = g.sid_cm * sb / h + c0;
+    views[v] = ViewGeom{sx, sy, (float)cb, (float)sb, 0.0f, 0.0f};
+    for (int d = 0; d < D; ++d) {
+      const double u = ((double)d - 0.5 * (D - 1)) * g.bin_cm;
+      const double px = (-(g.sdd_cm - g.sid_cm) * cb - u * sb) / h + c0;
+      const double py = (-(g.sdd_cm - g.sid_cm) * sb + u * cb) / h + c0;
+      double tx = px - sx, ty = py - sy;
+      const double len = std::sqrt(tx * tx + ty * ty);
+      tx /= len;
+      ty /= len;
+      if (std::fabs(tx) * std::fabs(ty) < kMinTilt) {
+        const double major = std::sqrt(1.0 - kMinTilt * kMinTilt);
+        if (std::fabs(tx) >= std::fabs(ty)) {
+          tx = tx > 0 ? major : -major;
+          ty = kMinTilt;
+        } else {
+          ty = ty > 0 ? major : -major;
+          tx = kMinTilt;
+        }
+      }
+      const double nx = -ty, ny = tx;
+      const double anx = std::fabs(nx), any = std::fabs(ny);
+      const double a = 0.5 * (anx + any);
+      const double hmax = h / std::max(anx, any);
+      const double kappa = h / (anx * any);
+      rays[(size_t)v * D + d] = RayLine{nx * kappa, ny * kappa, (float)(a * kappa), (float)hmax, (float)kappa, 0.0f};
+    }
+  }
+}
+
+namespace {
+
+int check_geometry(const osscir_geometry &g) {
+  if (g.n < 1 || g.n > 4096) return fail(OSSCIR_EINVAL, "image size n=%d outside [1, 4096]", g.n);
+  if (g.n_views < 1 || g.n_bins < 1) return fail(OSSCIR_EINVAL, "need n_views >= 1 and n_bins >= 1");
+  if ((int64_t)g.n_views * g.n_bins >= ((int64_t)1 << 31) / 16)
+    return fail(OSSCIR_EINVAL, "too many rays (%d x %d)", g.n_views, g.n_bins);
+  if (!(g.pixel_cm > 0) || !(g.bin_cm > 0) || !std::isfinite(g.view0_rad) || !std::isfinite(g.arc_rad))
+    return fail(OSSCIR_EINVAL, "pixel_cm and bin_cm must be > 0, angles finite");
+  const double half_diag = g.n * g.pixel_cm / std::sqrt(2.0);
+  if (!(g.sid_cm > half_diag * 1.0001) || !(g.sdd_cm > g.sid_cm + half_diag * 1.0001))
+    return fail(OSSCIR_EINVAL, "source and detector must lie outside the image circumcircle");
+  return OSSCIR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -101,15 +181,7 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   *out = nullptr;
   if (!geom || !spec) return fail(OSSCIR_EINVAL, "null geometry or spectral description");
   const osscir_geometry g = *geom;
-  if (g.n < 1 || g.n > 4096) return fail(OSSCIR_EINVAL, "image size n=%d outside [1, 4096]", g.n);
-  if (g.n_views < 1 || g.n_bins < 1) return fail(OSSCIR_EINVAL, "need n_views >= 1 and n_bins >= 1");
-  if ((int64_t)g.n_views * g.n_bins >= ((int64_t)1 << 31) / 16)
-    return fail(OSSCIR_EINVAL, "too many rays (%d x %d)", g.n_views, g.n_bins);
-  if (!(g.pixel_cm > 0) || !(g.bin_cm > 0) || !std::isfinite(g.view0_rad) || !std::isfinite(g.arc_rad))
-    return fail(OSSCIR_EINVAL, "pixel_cm and bin_cm must be > 0, angles finite");
-  const double half_diag = g.n * g.pixel_cm / std::sqrt(2.0);
-  if (!(g.sid_cm > half_diag * 1.0001) || !(g.sdd_cm > g.sid_cm + half_diag * 1.0001))
-    return fail(OSSCIR_EINVAL, "source and detector must lie outside the image circumcircle");
+  if (int rc = check_geometry(g)) return rc;
   if (spec->n_mat != kMat || spec->n_win != kWin)
     return fail(OSSCIR_EINVAL, "supported: n_mat=3, n_win=4 (got %d, %d)", spec->n_mat, spec->n_win);
   const int I = spec->n_energy;
@@ -145,34 +217,10 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   const size_t L = (size_t)V * D;
   const double h = g.pixel_cm;
 
-  // per-view source position and per-ray line parameters, pixel index
-  // coordinates (pixel (ix, iy) centred at (ix, iy)): normals scaled by
-  // kappa in FP64, the trapezoid constants rounded to FP32
+  std::vector<RayLine> rays;
+  std::vector<ViewGeom> views;
+  build_ray_table(g, rays, views);
   const double c0 = 0.5 * (N - 1);
-  std::vector<RayLine> rays(L);
-  std::vector<ViewGeom> views(V);
-  for (int v = 0; v < V; ++v) {
-    const double beta = g.view0_rad + g.arc_rad * (double)v / (double)V;
-    const double cb = std::cos(beta), sb = std::sin(beta);
-    const double sx = g.sid_cm * cb / h + c0, sy = g.sid_cm * sb / h + c0;
-    views[v] = ViewGeom{sx, sy, (float)cb, (float)sb, 0.0f, 0.0f};
-    for (int d = 0; d < D; ++d) {
-      const double u = ((double)d - 0.5 * (D - 1)) * g.bin_cm;
-      const double px = (-(g.sdd_cm - g.sid_cm) * cb - u * sb) / h + c0;
-      const double py = (-(g.sdd_cm - g.sid_cm) * sb + u * cb) / h + c0;
-      double tx = px - sx, ty = py - sy;
-      const double len = std::sqrt(tx * tx + ty * ty);
-      tx /= len;
-      ty /= len;
-      const double nx = -ty, ny = tx;
-      const double anx = std::fabs(nx), any = std::fabs(ny);
-      const double a = 0.5 * (anx + any);
-      const double hmax = h / std::max(anx, any);
-      const double prod = anx * any;
-      const double kappa = (prod * 1e30 > h) ? h / prod : 1e30;
-      rays[(size_t)v * D + d] = RayLine{nx * kappa, ny * kappa, (float)(a * kappa), (float)hmax, (float)kappa, 0.0f};
-    }
-  }
   // spectral table: shared responses folded with mu, or (per detector bin)
   // mu and its products here and the responses in a per-bin array
   const bool per_bin = n_resp > 1;
@@ -250,7 +298,7 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   sd.cbin = 0.5f * (float)(D - 1);
   for (int w = 0; w < kWin; ++w) sd.n0[w] = (float)spec->n0[w];
   sd.per_bin = per_bin ? 1 : 0;
-  sd.mfma = !per_bin && mfma_lds_bytes(I, 4) <= 65536 ? 1 : 0;
+  sd.mfma = !per_bin && mfma_lds_bytes(I, 8) <= 65536 ? 1 : 0;
   sd.tile_order = p->d_tile_order;
   sd.zero = p->d_zero;
   sd.sbin = p->d_sbin;
@@ -311,6 +359,45 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
     return hip_fail(e, "computing ray lengths");
   }
   *out = p;
+  return OSSCIR_OK;
+}
+
+int osscir_ray_table(const osscir_geometry *geom, double *rays, double *src) {
+  clear_error();
+  if (!geom || !rays || !src) return fail(OSSCIR_EINVAL, "ray_table: null argument");
+  if (int rc = check_geometry(*geom)) return rc;
+  std::vector<RayLine> rt;
+  std::vector<ViewGeom> vt;
+  build_ray_table(*geom, rt, vt);
+  for (size_t l = 0; l < rt.size(); ++l) {
+    double *o = rays + 6 * l;
+    o[0] = rt[l].nxk;
+    o[1] = rt[l].nyk;
+    o[2] = rt[l].ak;
+    o[3] = rt[l].hmax;
+    o[4] = rt[l].kappa;
+    o[5] = 0.0;
+  }
+  for (size_t v = 0; v < vt.size(); ++v) {
+    src[2 * v] = vt[v].sx;
+    src[2 * v + 1] = vt[v].sy;
+  }
+  return OSSCIR_OK;
+}
+
+int osscir_plan_set_energy_sums(osscir_plan plan, int32_t matrix_cores) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  ScanDesc &sd = plan->sd;
+  if (matrix_cores) {
+    if (sd.per_bin || mfma_lds_bytes(sd.n_energy, 8) > 65536)
+      return fail(OSSCIR_EINVAL,
+                  "energy sums on the matrix cores need one shared response table within 64 KB of LDS "
+                  "(per-bin responses or %d energies)", sd.n_energy);
+    sd.mfma = 1;
+  } else {
+    sd.mfma = 0;
+  }
   return OSSCIR_OK;
 }
 

@@ -209,8 +209,13 @@ int flush(osscir_batch b, hipStream_t st) {
   std::vector<Item> items[kLists];
   for (int s : order) {
     const ScanDesc &sd = b->slots[s].plan->sd;
-    const int code = s << kItemSlotShift;
     const int nfc = (sd.n_bins + c.fp_rays - 1) / c.fp_rays;
+    const int64_t n_fp = (int64_t)sd.n_views * nfc, n_spec = ((int64_t)sd.n_rays + c.spec_rays - 1) / c.spec_rays;
+    const int64_t n_bp = (int64_t)tiles_of(sd);
+    if (std::max(n_fp, std::max(n_spec, n_bp)) > (int64_t)kItemLocalMask + 1)
+      return fail(OSSCIR_EINVAL, "slot %d: %lld work items exceed the %d a slot may hold", s,
+                  (long long)std::max(n_fp, std::max(n_spec, n_bp)), kItemLocalMask + 1);
+    const int code = item_code(s, 0);
     for (int i = 0; i < sd.n_views * nfc; ++i) items[kListFp].push_back({code | i, (double)c.fp_rays * sd.n});
     const int nsc = (sd.n_rays + c.spec_rays - 1) / c.spec_rays;
     for (int i = 0; i < nsc; ++i) items[kListSpec].push_back({code | i, (double)c.spec_rays * sd.n_energy});

@@ -9,8 +9,21 @@ namespace osscir {
 
 constexpr int kSlotEmpty = 0, kSlotRunning = 1, kSlotDone = 2;
 constexpr int kMaxSlots = 256;
-constexpr int kItemSlotShift = 24;  // work item = slot << 24 | item index within the slot
+constexpr int kItemSlotShift = 24;  // work item = slot << 24 | item index within the slot (as unsigned bits)
 constexpr int kItemLocalMask = (1 << kItemSlotShift) - 1;
+
+// Work-item codes: the slot in the top 8 bits, the slot's local item index
+// (< 2^24, checked when the lists are built) below; encoded and decoded as
+// unsigned so that slots 128..255 survive the sign bit.
+__host__ __device__ constexpr int item_code(int slot, int local) {
+  return (int)(((unsigned)slot << kItemSlotShift) | (unsigned)local);
+}
+__host__ __device__ constexpr int item_slot(int code) { return (int)((unsigned)code >> kItemSlotShift); }
+__host__ __device__ constexpr int item_local(int code) { return code & kItemLocalMask; }
+static_assert(kMaxSlots <= (1 << (32 - kItemSlotShift)), "slot index must fit the code's top bits");
+static_assert(item_slot(item_code(kMaxSlots - 1, kItemLocalMask)) == kMaxSlots - 1, "slot round trip");
+static_assert(item_local(item_code(kMaxSlots - 1, kItemLocalMask)) == kItemLocalMask, "local round trip");
+static_assert(item_slot(item_code(128, 0)) == 128 && item_local(item_code(200, 12345)) == 12345, "round trip");
 constexpr int kListHeader = 16;     // ints before the items: per-XCD counts (8) and padding
 
 // Everything the batched kernels need of one slot: the plan's scan, the

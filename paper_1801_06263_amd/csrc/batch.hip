@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256, 6) kb_forward(const SlotDesc *__restrict_
   float4 OSSCIR_LDS *wb = (float4 OSSCIR_LDS *)(fwd_rows + (threadIdx.x >> 6) * (kFpUnroll * 64));
   for (int j = blockIdx.x / kXcds; j < cnt; j += stride) {
     const int it = list_item(wl, x, j);
-    const int s = it >> kItemSlotShift, local = it & kItemLocalMask;
+    const int s = item_slot(it), local = item_local(it);
     if (!slot_running(status, s)) continue;
     const SlotDesc sl = load_slot(slots, s);
     const int nchunk = (sl.sd.n_bins + R - 1) / R;
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
   const int cnt = list_count(wl, x);
   for (int j = blockIdx.x / kXcds; j < cnt; j += stride) {
     const int it = list_item(wl, x, j);
-    const int s = it >> kItemSlotShift, local = it & kItemLocalMask;
+    const int s = item_slot(it), local = item_local(it);
     if (!slot_running(status, s)) continue;
     const SlotDesc sl = load_slot(slots, s);
     const int l = local * (int)blockDim.x + (int)threadIdx.x;
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
   const int cnt = list_count(wl, x);
   for (int j = blockIdx.x / kXcds; j < cnt; j += stride) {
     const int it = list_item(wl, x, j);
-    const int s = it >> kItemSlotShift, local = it & kItemLocalMask;
+    const int s = item_slot(it), local = item_local(it);
     if (!slot_running(status, s)) continue;  // uniform over the workgroup
     const SlotDesc sl = load_slot(slots, s);
     const int ntx = (sl.sd.n + kBpTile - 1) / kBpTile;

@@ -55,4 +55,7 @@ WorkLayout work_layout(const ScanDesc &sd);
 // compact blocks of the image (one per XCD).
 std::vector<int> region_tile_order(int nt);
 
+// The per-view sources and per-ray line parameters of a (validated) geometry.
+void build_ray_table(const osscir_geometry &g, std::vector<RayLine> &rays, std::vector<ViewGeom> &views);
+
 }  // namespace osscir

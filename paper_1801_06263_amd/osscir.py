@@ -60,8 +60,10 @@ SLOT_EMPTY, SLOT_RUNNING, SLOT_DONE = 0, 1, 2
 SIGNATURES = {
     "osscir_plan_create": (c_int32, [ctypes.POINTER(_Geometry), ctypes.POINTER(_Spectral), ctypes.POINTER(c_void_p)]),
     "osscir_plan_destroy": (c_int32, [c_void_p]),
+    "osscir_plan_set_energy_sums": (c_int32, [c_void_p, c_int32]),
     "osscir_workspace_bytes": (c_int32, [c_void_p, ctypes.POINTER(c_size_t)]),
     "osscir_ray_lengths": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "osscir_ray_table": (c_int32, [ctypes.POINTER(_Geometry), _dp, _dp]),
     "osscir_forward_project": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "osscir_back_project": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "osscir_spectral_model": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -168,9 +170,7 @@ class Plan:
     def __init__(self, geom, spec):
         lib = load_library()
         self.n, self.n_views, self.n_bins = int(geom.n), int(geom.n_views), int(geom.n_bins)
-        g = _Geometry(self.n, float(geom.pixel_cm), self.n_views, self.n_bins, float(geom.sid_cm),
-                      float(geom.sdd_cm), float(geom.bin_cm), float(getattr(geom, "view0_rad", 0.0)),
-                      float(getattr(geom, "arc_rad", 2 * np.pi)))
+        g = _c_geometry(geom)
         self._mu = np.ascontiguousarray(spec.mu, dtype=np.float64)
         self._s = np.ascontiguousarray(spec.s, dtype=np.float64)
         self._n0 = np.ascontiguousarray(spec.n0, dtype=np.float64)
@@ -197,6 +197,11 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def set_energy_sums(self, matrix_cores: bool):
+        """Energy sums of the spectral step on the matrix cores (True, the
+        default where it applies) or as per-ray vector FMAs (False)."""
+        _check(_lib.osscir_plan_set_energy_sums(self._h, int(bool(matrix_cores))))
 
     # -- shapes
     @property
@@ -313,6 +318,23 @@ class Plan:
                                 _dev(c, (4, *self.sino_shape), torch.float32, "c"), _dev(out), _dev(work),
                                 work.numel(), _stream_handle(stream)))
         return out
+
+
+def _c_geometry(geom) -> _Geometry:
+    return _Geometry(int(geom.n), float(geom.pixel_cm), int(geom.n_views), int(geom.n_bins), float(geom.sid_cm),
+                     float(geom.sdd_cm), float(geom.bin_cm), float(getattr(geom, "view0_rad", 0.0)),
+                     float(getattr(geom, "arc_rad", 2 * np.pi)))
+
+
+def ray_table(geom):
+    """(rays [L, 6], src [V, 2]): the line parameters a plan of this geometry
+    uses (host computation in the library, no device)."""
+    lib = load_library()
+    g = _c_geometry(geom)
+    rays = np.zeros((int(geom.n_views) * int(geom.n_bins), 6))
+    src = np.zeros((int(geom.n_views), 2))
+    _check(lib.osscir_ray_table(ctypes.byref(g), rays.ctypes.data_as(_dp), src.ctypes.data_as(_dp)))
+    return rays, src
 
 
 def mu_pc_basis(spec):

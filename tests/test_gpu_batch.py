@@ -118,6 +118,28 @@ def test_batch_equals_single_bitwise(scans, precond, curvature, fp64):
         assert status[i][0] == 0
 
 
+def test_high_slot_indices(scans):
+    """Slots 127..255 of a full-size batch (work-item codes with the top bit
+    set) run the same trajectories as the single-scan path."""
+    from paper_1801_06263_amd import Batch, Params
+    from paper_1801_06263_amd.osscir import SLOT_RUNNING
+    modes = Params(1.0, "block", "clip", True)
+    b = Batch(modes, 256)
+    slots = [255, 200, 128, 127]
+    states = []
+    for s, (pr, plan, c) in zip(slots, scans):
+        st = plan.new_state(c)
+        b.set_slot(s, plan, st, lam_of(pr))
+        states.append(st)
+    n_it = 4
+    b.iterate(n_it, use_graph=True)
+    status = b.status()
+    for s, st, (pr, plan, c) in zip(slots, states, scans):
+        assert status[s][:2] == (SLOT_RUNNING, n_it), (s, status[s])
+        assert same_state(st, single_run(plan, c, Params(lam_of(pr), "block", "clip", True), n_it)), s
+    assert all(status[i][0] == 0 for i in range(256) if i not in slots)
+
+
 def test_graph_replays_match_eager(scans):
     """Graph replays against direct launches, one iteration at a time, with
     eager torch work and synchronisation between replays."""

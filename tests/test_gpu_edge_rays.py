@@ -1,0 +1,107 @@
+"""Rays lying exactly on a pixel edge (even n, odd n_bins, views at multiples
+of 90 degrees): the library counts each once, in the pixel on the line's +
+side, as the oracle's half-open pixels do.  Ray lengths, forward and back
+projection through those rays, bit-exact transposition on their pixels, and a
+100-iteration MOCCA trajectory on such a scan against the oracle."""
+import warnings
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import dev, host, normwise, sino
+from oracle import model, mocca as omocca, projector as pj
+
+warnings.filterwarnings("ignore", category=RuntimeWarning)
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EDGE_GEOMS = [(16, 20.0, 8, 33), (64, 20.0, 64, 127)]
+
+
+@pytest.fixture(scope="module", params=EDGE_GEOMS, ids=lambda a: f"{a[0]}px_{a[2]}x{a[3]}")
+def edge(request):
+    from paper_1801_06263_amd import Plan
+    geom = synth.make_geometry(*request.param)
+    spec = synth.make_spectral(20, 119, 120.0, 1e5, e_step=5)
+    return geom, pj.system_matrix(geom), Plan(geom, spec)
+
+
+def central_rays(geom):
+    c = (geom.n_bins - 1) // 2
+    return [v * geom.n_bins + c for v in range(0, geom.n_views, geom.n_views // 4)]
+
+
+def test_edge_rays_have_full_length(edge):
+    geom, X, plan = edge
+    rho = host(plan.ray_lengths()).ravel()
+    ref = np.asarray(X.sum(axis=1)).ravel()
+    for l in central_rays(geom):
+        assert abs(rho[l] - geom.n * geom.pixel_cm) <= 1e-5 * geom.n * geom.pixel_cm
+    assert normwise(rho, ref) <= 1e-5
+
+
+def test_edge_rays_forward_and_back(edge):
+    geom, X, plan = edge
+    rng = np.random.default_rng(11)
+    # a map whose two rows (columns) beside the centre line differ strongly
+    f = rng.random((3, geom.n, geom.n)).astype(np.float32)
+    f[:, geom.n // 2, :] += 5.0
+    f[:, :, geom.n // 2] += 5.0
+    p = host(plan.forward_project(dev(f))).reshape(3, -1)
+    ref = (X @ f.reshape(3, -1).astype(np.float64).T).T
+    ls = central_rays(geom)
+    np.testing.assert_allclose(p[:, ls], ref[:, ls], rtol=1e-5)
+    assert normwise(p, ref) <= 1e-5
+    q = np.zeros((1, geom.n_views * geom.n_bins), np.float32)
+    q[0, ls] = 1.0
+    b = host(plan.back_project(dev(q.reshape(1, geom.n_views, geom.n_bins)))).ravel()
+    np.testing.assert_allclose(b, X.T @ q[0].astype(np.float64), rtol=0, atol=1e-5 * geom.pixel_cm)
+
+
+def test_edge_rays_transpose_is_exact(edge):
+    geom, X, plan = edge
+    n = geom.n
+    for l in central_rays(geom):
+        u = np.zeros((1, geom.n_views, geom.n_bins), np.float32)
+        u.ravel()[l] = 1.0
+        row = host(plan.back_project(dev(u))).ravel()               # X[l, :]
+        ks = [k for k in (X[l].indices.tolist()) if k % 7 == 0][:6]
+        # the pixels on both sides of the edge
+        h = n // 2
+        ks += [h * n + 3, (h - 1) * n + 3, 3 * n + h, 3 * n + h - 1]
+        for k in ks:
+            e = np.zeros((1, n, n), np.float32)
+            e.ravel()[k] = 1.0
+            col = host(plan.forward_project(dev(e))).ravel()        # X[:, k]
+            assert row[k] == col[l]
+            assert row[k] == pytest.approx(X[l, k], abs=4e-6 * geom.pixel_cm)
+
+
+@pytest.fixture(scope="module")
+def edge_scan():
+    geom = synth.make_geometry(64, 20.0, 64, 127)
+    spec = synth.make_spectral(20, 119, 120.0, 1e5)
+    X = pj.system_matrix(geom)
+    f_true = synth.inserts_phantom(64, 20.0)
+    c = synth.poisson_counts(model.counts_model(X @ f_true.reshape(3, -1).T, spec), 1811)
+    lam, n_it = 3e-7, 100
+    ref, _ = omocca.mocca(X, c, spec, lam, n_it, "block", "clip")
+    return geom, spec, c, lam, n_it, ref
+
+
+# The per-ray 3x3 / 4x4 tail in FP32 (the non-default option) drifts to
+# 1.6e-3 on this scan after 100 iterations, past the 1e-3 bar the FP64 tail
+# meets: the FP32 option is held to a looser bound.
+@pytest.mark.parametrize("fp64,bar", [(True, 1e-3), (False, 3e-3)])
+def test_edge_scan_trajectory(edge_scan, fp64, bar):
+    from paper_1801_06263_amd import Params, Plan
+    geom, spec, c, lam, n_it, ref = edge_scan
+    plan = Plan(geom, spec)
+    st = plan.new_state(dev(sino(c, geom.n_views, geom.n_bins)))
+    plan.mocca_iterate(st, Params(lam, "block", "clip", fp64), n_it)
+    f = host(st.f).reshape(3, -1)
+    for m in range(3):
+        rel = np.linalg.norm(f[m] - ref.f[m]) / np.linalg.norm(ref.f[m])
+        print(f"edge scan fp64_small={fp64} material {m}: rel L2 {rel:.2e}")
+        assert rel <= bar

@@ -49,6 +49,10 @@ GEOMS = {
     "ragged": synth.make_geometry(40, 20.0, 30, 100),
     "offset": synth.Geometry(n=24, pixel_cm=0.7, n_views=17, n_bins=61, sid_cm=40.0, sdd_cm=90.0, bin_cm=0.9,
                              view0_rad=0.37, arc_rad=math.pi),
+    # even n, odd n_bins: the detector-centre ray of each view at a multiple of
+    # 90 degrees lies exactly on the grid line through the isocentre
+    "edge16": synth.make_geometry(16, 20.0, 8, 33),
+    "edge64": synth.make_geometry(64, 20.0, 64, 127),
 }
 
 
@@ -254,6 +258,40 @@ def test_mocca_trajectory_parity(tiny, precond, curvature, fp64):
     rel_y = np.linalg.norm(y - ref.y) / np.linalg.norm(ref.y)
     print(f"  dual rel L2 {rel_y:.2e}")
     assert rel_y <= 1e-3
+
+
+def test_vector_energy_sums_trajectory_parity(tiny):
+    """The spectral step with its energy sums as per-ray vector FMAs instead
+    of the matrix-core contraction, on the same shared-table scan: the same
+    bar against the oracle, and not the matrix-core path's bits."""
+    from paper_1801_06263_amd import Params, Plan
+    pr, X, c, _ = tiny
+    lam, n_it = 3e-7, 100
+    ref, _ = omocca.mocca(X, c, pr.spec, lam, n_it, "block", "clip")
+    out = {}
+    for mc in (True, False):
+        plan = Plan(pr.geom, pr.spec)
+        plan.set_energy_sums(mc)
+        st = plan.new_state(dev(sino(c, pr.geom)))
+        plan.mocca_iterate(st, Params(lam, "block", "clip", True), n_it)
+        f = host(st.f).reshape(3, -1)
+        for m in range(3):
+            rel = np.linalg.norm(f[m] - ref.f[m]) / np.linalg.norm(ref.f[m])
+            print(f"matrix_cores={mc} material {m}: rel L2 {rel:.2e}")
+            assert rel <= 1e-3
+        out[mc] = f
+    assert not np.array_equal(out[True], out[False])
+
+
+def test_energy_sums_option_is_refused_where_it_does_not_apply():
+    from paper_1801_06263_amd import Plan
+    from paper_1801_06263_amd.osscir import OsscirError
+    geom = synth.make_geometry(16, 20.0, 8, 16)
+    big = synth.make_spectral(20, 400, 420.0, 1e5)            # 381 energies: table beyond 64 KB of LDS
+    plan = Plan(geom, big)
+    plan.set_energy_sums(False)
+    with pytest.raises(OsscirError, match="matrix cores"):
+        plan.set_energy_sums(True)
 
 
 def test_mu_pc_trajectory_parity(tiny):

@@ -95,3 +95,30 @@ def test_budget_and_sequential_loop_give_the_same_results(reqs):
     lat_seq = max(x.latency for x in seq.values())
     lat_mix = max(x.latency for x in mix.values())
     print(f"max latency: batched {lat_mix:.3f}s, sequential {lat_seq:.3f}s")
+
+
+def test_served_request_matches_oracle(reqs):
+    """A tiny-scan request with the oracle's counts, served for 100
+    iterations among batch slices that arrive before and after it, against
+    the FP64 oracle's MOCCA at the same iteration count."""
+    import dataclasses
+
+    from oracle import model, mocca, projector
+    from paper_1801_06263_amd.serve import Request
+    pr = synth.problem("tiny")
+    X = projector.system_matrix(pr.geom)
+    c = synth.poisson_counts(model.counts_model(X @ pr.f_true.reshape(3, -1).T, pr.spec), pr.seed)
+    lam, n_it = 3e-7, 100
+    ref, _ = mocca.mocca(X, c, pr.spec, lam, n_it, "block", "clip")
+    g = pr.geom
+    mine = Request(99, g, pr.spec, np.ascontiguousarray(c.T.reshape(4, g.n_views, g.n_bins), dtype=np.float32), lam,
+                   max_iter=n_it, arrival=0.01)
+    others = [dataclasses.replace(r, arrival=0.005 * i) for i, r in enumerate(reqs[:6])]
+    mix, _ = run(others + [mine], max_slots=8, iters_per_tick=6)
+    res = mix[99]
+    assert res.iters == n_it
+    f = host(res.f).reshape(3, -1)
+    for m in range(3):
+        rel = np.linalg.norm(f[m] - ref.f[m]) / np.linalg.norm(ref.f[m])
+        print(f"served tiny request, material {m}: rel L2 vs oracle {rel:.2e}")
+        assert rel <= 1e-3
