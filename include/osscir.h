@@ -214,6 +214,20 @@ int osscir_diag_spc_steps(osscir_plan plan, const float *G, double lambda, float
 int osscir_mocca_iterate(osscir_plan plan, const osscir_params *params, osscir_state *state, int32_t n_iter,
                          double *dtpl, osscir_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): exactly
+ * osscir_mocca_iterate (same kernels, same results bit for bit) on the state
+ * buffers f, fbar, y (updated in place) and c, with the workspace taken
+ * from a static device array of 64 MiB that the library holds on every
+ * device it runs on until the process ends (enough for the 512^2,
+ * 720 x 1024 scan, which needs 50.5 MiB).  Calls no allocating routine.
+ * EINVAL if the plan's workspace (osscir_workspace_bytes) exceeds 64 MiB.
+ * Every call on one device shares that device's array and leaves the last
+ * call's contents in it (each call writes all it reads first): calls that
+ * overlap on one device race, so issue them on one stream, or order them. */
+int osscir_mocca_iterate_noalloc(osscir_plan plan, const osscir_params *params, float *f, float *fbar, float *y,
+                                 const float *c, int32_t n_iter, double *dtpl, osscir_stream stream);
+
 /* One stage of a MOCCA iteration, exactly as osscir_mocca_iterate runs it:
  *   stage 0  forward projection p = X fbar into the workspace
  *   stage 1  spectral model, step lengths and dual step (reads p, updates y)

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libosscir.so")
 ARCH = os.environ.get("OSSCIR_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "batch.cpp", "projector.hip", "spectral.hip", "batch.hip"]
+SOURCES = ["api.cpp", "batch.cpp", "projector.hip", "spectral.hip", "batch.hip", "noalloc.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

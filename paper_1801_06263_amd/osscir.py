@@ -75,6 +75,8 @@ SIGNATURES = {
     "osscir_mocca_iterate": (c_int32, [c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_State), c_int32, c_void_p,
                                        c_void_p]),
     "osscir_mocca_stage": (c_int32, [c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_State), c_int32, c_void_p]),
+    "osscir_mocca_iterate_noalloc": (c_int32, [c_void_p, ctypes.POINTER(_Params), c_void_p, c_void_p, c_void_p,
+                                               c_void_p, c_int32, c_void_p, c_void_p]),
     "osscir_ray_nnz": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "osscir_dtpl": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "osscir_mu_pc_basis": (c_int32, [ctypes.POINTER(_Spectral), _dp, _dp]),
@@ -294,6 +296,22 @@ class Plan:
         _check(_lib.osscir_mocca_iterate(self._h, ctypes.byref(prm), ctypes.byref(st), int(n_iter),
                                          _dev(out) if dtpl else None, _stream_handle(stream)))
         return out
+
+    def mocca_iterate_noalloc(self, state: State, params: Params, n_iter: int, dtpl=None, stream=None):
+        """As mocca_iterate, with the library's static scratch in place of
+        state.work (which is not touched); dtpl: an optional [n_iter]
+        float64 device tensor the caller allocated."""
+        import torch
+        V, D = self.sino_shape
+        if dtpl is not None:
+            _dev(dtpl, (max(n_iter, 1),), torch.float64, "dtpl")
+        prm = params.to_c()
+        _check(_lib.osscir_mocca_iterate_noalloc(
+            self._h, ctypes.byref(prm), _dev(state.f, (3, self.n, self.n), torch.float32, "f"),
+            _dev(state.fbar, (3, self.n, self.n), torch.float32, "fbar"),
+            _dev(state.y, (4, V, D), torch.float32, "y"), _dev(state.c, (4, V, D), torch.float32, "c"),
+            int(n_iter), _dev(dtpl) if dtpl is not None else None, _stream_handle(stream)))
+        return dtpl
 
     def mocca_stage(self, state: State, params: Params, stage: int, stream=None):
         """One stage (0 forward projection, 1 spectral + dual, 2 back-projection + primal)."""
