@@ -84,6 +84,7 @@ void free_plan(osscir_plan p) {
   if (p->d_n0bin) (void)hipFree(p->d_n0bin);
   if (p->d_tile_order) (void)hipFree(p->d_tile_order);
   if (p->d_zero) (void)hipFree(p->d_zero);
+  if (p->d_tile_bins) (void)hipFree(p->d_tile_bins);
   delete p;
 }
 
@@ -122,7 +123,11 @@ void osscir::build_ray_table(const osscir_geometry &g, std::vector<RayLine> &ray
   for (int v = 0; v < V; ++v) {
     double cb, sb;
     view_cos_sin(g.view0_rad + g.arc_rad * (double)v / (double)V, cb, sb);
-    const double sx = g.sid_cm * cb / h + c0, sy = g.sid_cm * sb / h + c0;
+    // the source on a 2^-30-pixel grid: with |s| < 2^22 every offset s - i
+    // to an integer pixel index is then exact in FP64, so the kernels may
+    // step offsets by whole pixels and still agree bit for bit
+    const double sx = std::ldexp(std::nearbyint(std::ldexp(g.sid_cm * cb / h + c0, 30)), -30);
+    const double sy = std::ldexp(std::nearbyint(std::ldexp(g.sid_cm * sb / h + c0, 30)), -30);
     views[v] = ViewGeom{sx, sy, (float)cb, (float)sb, 0.0f, 0.0f};
     for (int d = 0; d < D; ++d) {
       const double u = ((double)d - 0.5 * (D - 1)) * g.bin_cm;
@@ -164,6 +169,8 @@ int check_geometry(const osscir_geometry &g) {
   const double half_diag = g.n * g.pixel_cm / std::sqrt(2.0);
   if (!(g.sid_cm > half_diag * 1.0001) || !(g.sdd_cm > g.sid_cm + half_diag * 1.0001))
     return fail(OSSCIR_EINVAL, "source and detector must lie outside the image circumcircle");
+  if (!(g.sid_cm / g.pixel_cm + g.n < 4194304.0))
+    return fail(OSSCIR_EINVAL, "source farther than 2^22 pixels from the image");
   return OSSCIR_OK;
 }
 
@@ -342,6 +349,19 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   sd.views = p->d_views;
   sd.rho = p->d_rho;
   sd.tab = p->d_tab;
+  sd.tile_bins = nullptr;
+  if (!sd.bp_wide) {
+    // staged bins of every (tile, view), once per plan
+    if ((e = hipMalloc(&p->d_tile_bins, tile_bins_count(sd) * sizeof(TileBins))) != hipSuccess) {
+      free_plan(p);
+      return fail(OSSCIR_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+    if ((e = launch_tile_bins(sd, p->d_tile_bins, nullptr)) != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "tabulating the back-projection tiles");
+    }
+    sd.tile_bins = p->d_tile_bins;
+  }
 
   // rho = X 1 with the library's own projector
   float *ones = nullptr;

@@ -161,53 +161,60 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
 }
 
 // The walk of a full wave (all lanes on one major axis, no ray near 45
-// degrees) with the image read through LDS.  In a column the crossing is
-// monotonic in the bin, so the candidate rows of the wave's 64 rays form one
-// run [r0, r1] bounded by its first and last lanes; lane j copies row r0 + j
-// of the packed image straight into the wave's LDS rows (a 16-byte
-// global-to-LDS load: no VGPRs, one copy of a pixel that neighbouring rays
-// share), and each lane then reads its two candidates from LDS.  Where
-// neighbouring rays are under a pixel apart (1024 bins over a 512^2 image:
-// a run of ~35 rows) the texture path moves a third of the bytes of two
-// 12-byte loads per lane.  A step where some lane's candidates fall outside the
-// copied run (a run longer than 64 rows, rounding at the ends) reads the
-// same pixels directly, so the products and their order are exactly those of
+// degrees) with the image read through LDS.  At a column the crossing is
+// monotonic in the bin, and along the walk it is linear in the column, so
+// over a step of kFpUnroll columns the candidate rows of the wave's 64 rays
+// lie between the crossings of its first and last lanes at the step's first
+// and last columns.  The step copies that window of rows (one row per lane,
+// 16-byte global-to-LDS loads from a scalar base: no VGPRs, one copy of a
+// pixel that neighbouring rays share) for each of its columns, and each lane
+// reads its two candidates per column from LDS.  The window keeps one row of
+// margin on each side for crossings that FP32 rounding moves across a row
+// boundary; a step whose window exceeds 64 rows reads the same pixels
+// directly, so the products and their order are exactly those of
 // forward_walk.
+//
+// The source lies on a 2^-30-pixel grid (the plan rounds it there), so
+// every offset s - i is exact in FP64: the column offset steps by -1 and the
+// second candidate's offset is the first's minus one, with the same bits as
+// the back-projector's per-pixel offsets.
 template <bool XMAJOR>
 __device__ __forceinline__ void forward_walk_lds(int lo, int hi, int n, const float4 *__restrict__ img, double s_u,
                                                  double s_v, float slope, float base, const RayLine &ray, double &s0,
                                                  double &s1, double &s2, float4 OSSCIR_LDS *wb) {
+  static_assert(kFpUnroll == 4, "the step window is bounded at its first and last column");
   const int np = n + 2 * kPad;
   const int lane = (int)__lane_id();
   float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
   int pairs = 0;
+  double du0 = s_u - (double)lo;  // exact
   for (int u = lo; u <= hi; u += kFpUnroll) {
-    int iv0s[kFpUnroll], slot[kFpUnroll];
-    bool bad = false;
-    __builtin_amdgcn_s_waitcnt(0);  // the previous step's reads of wb have completed
+    int iv0s[kFpUnroll];
 #pragma unroll
     for (int k = 0; k < kFpUnroll; ++k) {
-      const int uu = u + k;
-      const float ys = __fmaf_rn(slope, (float)uu, base);
-      const int iv0 = floor_to_int(__builtin_amdgcn_fmed3f(ys, -2.0f, (float)n));  // in [-2, n]
-      const int rf = __builtin_amdgcn_readlane(iv0, 0), rl = __builtin_amdgcn_readlane(iv0, 63);
-      const int r0 = min(rf, rl) - 1;  // >= -3
-      const int span = max(rf, rl) - r0 + 2;  // rows r0 .. r1 = max + 1 (lanes past them copy nothing)
-      const int rowp = min(r0 + kPad + lane, np - 1);
-      if (lane < span)
-        __builtin_amdgcn_global_load_lds(img + (size_t)(uu + kPad) * np + rowp, wb + k * 64, 16, 0, 0);
-      iv0s[k] = iv0;
-      slot[k] = iv0 - r0;
-      bad = bad || (unsigned)slot[k] > (unsigned)(min(span, 64) - 2);  // both candidates among the copied rows
+      const float ys = __fmaf_rn(slope, (float)(u + k), base);
+      iv0s[k] = floor_to_int(__builtin_amdgcn_fmed3f(ys, -2.0f, (float)n));  // in [-2, n]
+    }
+    // the step's rows r0 .. r0 + span - 1 (r0 >= -3, r0 + span - 1 <= n + 2)
+    const int c00 = __builtin_amdgcn_readlane(iv0s[0], 0), c01 = __builtin_amdgcn_readlane(iv0s[0], 63);
+    const int c30 = __builtin_amdgcn_readlane(iv0s[kFpUnroll - 1], 0);
+    const int c31 = __builtin_amdgcn_readlane(iv0s[kFpUnroll - 1], 63);
+    const int r0 = min(min(c00, c01), min(c30, c31)) - 1;
+    const int span = max(max(c00, c01), max(c30, c31)) - r0 + 3;
+    const bool via_lds = span <= 64;  // uniform
+    __builtin_amdgcn_s_waitcnt(0);    // the previous step's reads of wb have completed
+    if (via_lds && lane < span) {
+      const float4 *col = img + ((size_t)(u + kPad) * np + (r0 + kPad)) + lane;
+#pragma unroll
+      for (int k = 0; k < kFpUnroll; ++k)
+        __builtin_amdgcn_global_load_lds(col + (size_t)k * np, wb + k * 64, 16, 0, 0);
     }
     float w[kFpUnroll][2];
 #pragma unroll
     for (int k = 0; k < kFpUnroll; ++k) {
-      const int uu = u + k;
-      const double du = s_u - (double)uu;
-      const double fv0 = (double)iv0s[k];
-      const double dv0 = s_v - fv0;
-      const double dv1 = s_v - (fv0 + 1.0);
+      const double du = du0 - (double)k;  // exact
+      const double dv0 = s_v - (double)iv0s[k];
+      const double dv1 = dv0 - 1.0;      // exact
       if (XMAJOR) {
         w[k][0] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, du, dv0);
         w[k][1] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, du, dv1);
@@ -218,12 +225,13 @@ __device__ __forceinline__ void forward_walk_lds(int lo, int hi, int n, const fl
     }
     float4 fv[kFpUnroll][2];
     __builtin_amdgcn_s_waitcnt(0);  // the copies have landed in LDS
-    if (!__any(bad)) {
-      const float4 *wr = (const float4 *)wb;  // generic view of the LDS rows (reads stay ds_read)
+    if (via_lds) {
+      // generic view of the LDS rows (reads stay ds_read); slot of row r: r - r0
+      const float4 *wr = (const float4 *)wb - r0;
 #pragma unroll
       for (int k = 0; k < kFpUnroll; ++k) {
-        fv[k][0] = wr[k * 64 + slot[k]];
-        fv[k][1] = wr[k * 64 + slot[k] + 1];
+        fv[k][0] = wr[k * 64 + iv0s[k]];
+        fv[k][1] = wr[k * 64 + iv0s[k] + 1];
       }
     } else {
 #pragma unroll
@@ -249,6 +257,7 @@ __device__ __forceinline__ void forward_walk_lds(int lo, int hi, int n, const fl
       a0 = a1 = a2 = 0.0f;
       pairs = 0;
     }
+    du0 -= (double)kFpUnroll;
   }
   s0 += (double)a0;
   s1 += (double)a1;

@@ -11,6 +11,16 @@ namespace osscir {
 
 struct RayLine;
 
+// Bins of one view staged for one 16 x 16 back-projection tile (common
+// path): the rays that can meet the tile are bins d0 .. d0 + nst - 1, a
+// pixel's window starts at staged index floor(bin_scale t + off) (t its
+// centre's detector coordinate) and holds K bins.  One per (tile, view),
+// computed once per plan.
+struct TileBins {
+  int d0, nst, K;
+  float off;
+};
+
 // Per-view geometry: source position in pixel index coordinates (pixel
 // (ix, iy) centred at (ix, iy)), and the view direction for the detector
 // projection of pixel corners.
@@ -72,6 +82,7 @@ struct ScanDesc {
   const float4 *sbin;   // [I][D] s_{w,d,i} (w = x, y, z, w), per_bin only
   const float4 *n0bin;  // [D] incident counts per window, per_bin only
   const int *tile_order;  // [nt * nt] back-projection tiles (ty * nt + tx) in region order
+  const TileBins *tile_bins;  // [nt * nt][V] staged bins per (tile, view); null on the wide path
   const float4 *zero;     // 256 bytes of zeros (a null ray record and null inputs)
   const struct RayLine *rays;  // [L]
   const ViewGeom *views;        // [V]

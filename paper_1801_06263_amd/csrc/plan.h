@@ -23,6 +23,7 @@ struct osscir_plan_s {
   float4 *d_n0bin = nullptr;  // per-detector-bin incident counts [D]
   int *d_tile_order = nullptr;  // back-projection tiles in region order
   float4 *d_zero = nullptr;     // 256 zero bytes the back-projector stages for empty slots
+  osscir::TileBins *d_tile_bins = nullptr;  // staged bins per (tile, view) of the common back-projection path
 };
 
 namespace osscir {

@@ -3,10 +3,10 @@
 // step lengths) into it.
 //
 // A workgroup owns a 16 x 16 pixel tile, one thread per pixel, and walks the
-// views in order.  For a chunk of views at a time, one thread per view
-// projects the tile's four corners onto the detector: every ray that meets
-// the tile has its bin inside that shadow (+0.05 bin), and the same corners
-// bound the half-width hw of every pixel's own shadow in that view.
+// views in order.  Projecting the tile's four corners onto the detector
+// bounds, for each view, the bins whose rays can meet the tile (+0.05 bin)
+// and the half-width hw of every pixel's own shadow; the plan does this once
+// for every (tile, view) (TileBins), the wide path per chunk of views.
 //
 // Common path: views are staged in groups of four, wave w staging the bins
 // of the group's view w into LDS (line parameters and the NCH input values,
@@ -16,14 +16,15 @@
 // barriers.  With qS as input (the fused primal step) and a grid of at least
 // four workgroups per CU, the bins are instead copied straight from memory
 // into double-buffered LDS arrays (global-to-LDS loads, one barrier per
-// group); both stagings hold the same records.  A pixel's non-zero weights in a view lie on the bins strictly
-// inside (tau - hw, tau + hw), tau being its centre's detector position: at
-// most K = floor(2 hw) + 1 consecutive bins.  Every thread reads, in each of
-// the group's views, a window of Kmax = max K of the group staged bins
-// starting at floor(tau - hw) + 1, clamped into the staged range; the bins of
-// a window outside the pixel's shadow have weight exactly 0.  Kmax is uniform
-// over the workgroup, so the loop carries no per-lane bounds or divergence,
-// and the four views' windows are independent work within a step.
+// group); both stagings hold the same records.  A pixel's non-zero weights in
+// a view lie on the bins strictly inside (tau - hw, tau + hw), tau being its
+// centre's detector position: at most K = floor(2 hw) + 1 consecutive bins.
+// Every thread reads the group's views in pairs, a pair's window of
+// max(K, K') staged bins starting at floor(tau - hw) + 1 in each view,
+// clamped into the staged range; the bins of a window outside the pixel's
+// shadow have weight exactly 0.  The window length is uniform over the
+// workgroup, so the loop carries no per-lane bounds or divergence, and the
+// two views' windows are independent work within a step.
 //
 // Wide path (some tile shadow exceeds 62 bins; chosen by the plan): one view
 // at a time, up to 128 bins staged by all four waves, each thread looping
@@ -330,18 +331,18 @@ __device__ __forceinline__ void back_accumulate_views(const ScanDesc &sd, int ti
   }
 }
 
-// Loads of the bin staged by this thread in a group: view j of the chunk
-// starting at vc (wave su of the group), bin d0 + sl.  A thread without a bin
-// (past the view's shadow, or past the chunk) loads the plan's zero record
-// instead, whose weight is exactly 0 (med3((0 - 0) * 0, 0, 0)), so every slot
-// of the group is rewritten and no branch or select on the data is needed.
+// Loads of the bin staged by this thread in a group: view j (wave su of the
+// group) with staged bins tb, bin d0 + sl.  A thread without a bin (past the
+// view's shadow, or past the last view) loads the plan's zero record
+// instead, whose weight is exactly 0 (med3((0 - 0) * 0, 0, 0)), so every
+// slot of the group is rewritten and no branch or select on the data is
+// needed.
 template <int NCH, bool QS12>
 __device__ __forceinline__ void group_load(const ScanDesc &sd, const float *__restrict__ q, unsigned q_stride,
-                                           unsigned nb, const BpShared &sh, int vc, int j, int cnt, int sl,
+                                           unsigned nb, const TileBins &tb, int j, bool valid, int sl,
                                            BinRegs<NCH> &b) {
-  const ViewTile vt = sh.vt[min(j, cnt - 1)];
-  const bool has = j < cnt && sl < min(vt.nst, kBpSlot);
-  const unsigned l = (unsigned)(vc + j) * nb + (unsigned)(vt.d0 + sl);  // used only if has
+  const bool has = valid && sl < min(tb.nst, kBpSlot);
+  const unsigned l = (unsigned)j * nb + (unsigned)(tb.d0 + sl);  // used only if has
   b.r = *(has ? sd.rays + l : reinterpret_cast<const RayLine *>(sd.zero));
   if (QS12) {
     const float4 *__restrict__ q4 = has ? reinterpret_cast<const float4 *>(q) + 3 * (size_t)l : sd.zero;
@@ -366,111 +367,16 @@ __device__ __forceinline__ void group_load(const ScanDesc &sd, const float *__re
   }
 }
 
-// Common path (every tile shadow within kBpSlot - 2 bins; the plan checks).
-template <int NCH, bool QS12>
-__device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int tile_x, int tile_y,
-                                                        const float *__restrict__ q, int q_stride_i, double acc[NCH],
-                                                        BpShared &sh) {
-  const int tid = threadIdx.x;
-  int tx, ty;
-  bp_pixel_of_thread(tid, tx, ty);
-  const int ix = tile_x * kBpTile + tx;
-  const int iy = tile_y * kBpTile + ty;
-  const int V = sd.n_views;
-  const unsigned nb = (unsigned)sd.n_bins, q_stride = (unsigned)q_stride_i;
-  const float X = (float)ix - sd.c0;  // centred, for the detector projection
-  const float Y = (float)iy - sd.c0;
-  const float sid = in_vgpr(sd.sid_px);
-  const double fx = (double)ix, fy = (double)iy;
-  const int su = tid >> 6, sl = tid & 63;  // staged slot: view su of the group, bin sl
-  static_assert(kBpGroup * 64 == kBpThreads && kBpSlot == 64, "one wave per view, one lane per bin");
-  static_assert(kBpViewChunk % kBpFlush == 0 && kBpFlush % kBpGroup == 0, "flushes at group ends");
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
-  for (int vc = 0; vc < V; vc += kBpViewChunk) {
-    const int cnt = min(kBpViewChunk, V - vc);
-    __syncthreads();  // the previous chunk is done with sh
-    if (tid < cnt) tile_view_bounds(sd, sd.views[vc + tid], tile_x, tile_y, sh.vt[tid]);
-    __syncthreads();
-    BinRegs<NCH> nxt;
-    group_load<NCH, QS12>(sd, q, q_stride, nb, sh, vc, su, cnt, sl, nxt);
-    float part[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) part[c] = 0.0f;
-    for (int g0 = 0; g0 < cnt; g0 += kBpGroup) {
-      __syncthreads();  // the previous group's windows have been read
-      bin_store<NCH>(nxt, sh.gbins[su][sl]);
-      __syncthreads();
-      group_load<NCH, QS12>(sd, q, q_stride, nb, sh, vc, g0 + kBpGroup + su, cnt, sl, nxt);
-      // the group's views: all reads first (views past the chunk repeat its
-      // last view with no staged bins: their slots hold zero records)
-      ViewTile vt[kBpGroup];
-      ViewGeom vg[kBpGroup];
-#pragma unroll
-      for (int u = 0; u < kBpGroup; ++u) {
-        const int j = min(g0 + u, cnt - 1);
-        vt[u] = sh.vt[j];
-        vg[u] = load_uniform(sd.views + vc + j);
-      }
-      float t[kBpGroup];
-      int nst[kBpGroup], s[kBpGroup];
-      double dx[kBpGroup], dy[kBpGroup];
-      int kmax = 0;
-#pragma unroll
-      for (int u = 0; u < kBpGroup; ++u) {
-        nst[u] = g0 + u < cnt ? min(__builtin_amdgcn_readfirstlane(vt[u].nst), kBpSlot) : 0;
-        kmax = max(kmax, min(__builtin_amdgcn_readfirstlane(vt[u].K), nst[u]));
-        const float num = __fmaf_rn(vg[u].cb, Y, -vg[u].sb * X);
-        const float den = __fmaf_rn(-vg[u].sb, Y, __fmaf_rn(-vg[u].cb, X, sid));
-        t[u] = __fmaf_rn(num * __builtin_amdgcn_rcpf(den), sd.bin_scale, vt[u].off);
-        dx[u] = vg[u].sx - fx;
-        dy[u] = vg[u].sy - fy;
-      }
-      // window u: [s, s + kmax) inside [0, max(nst, kmax)) within the slot,
-      // starting at floor(tau - hw) + 1: it covers the staged part of the
-      // pixel's shadow, the integers inside (tau - hw, tau + hw) (at most
-      // K <= kmax of them)
-      const BinLDS *wb[kBpGroup];  // window starts (s < 64: 24-bit multiplies)
-#pragma unroll
-      for (int u = 0; u < kBpGroup; ++u) {
-        s[u] = clamp_0_hi(floor_to_int(t[u]), max(0, nst[u] - kmax));
-        wb[u] = reinterpret_cast<const BinLDS *>(reinterpret_cast<const char *>(&sh.gbins[u][0]) +
-                                                 __umul24((unsigned)s[u], (unsigned)sizeof(BinLDS)));
-      }
-      const int kmx = __builtin_amdgcn_readfirstlane(kmax);  // uniform trip count: a scalar loop
-      for (int i = 0; i < kmx; ++i) {
-#pragma unroll
-        for (int u = 0; u < kBpGroup; u += 2) {
-          BinLDS e0, e1;  // two views' reads in flight before the first weight
-          load_bin<NCH>(wb[u][i], e0);
-          load_bin<NCH>(wb[u + 1][i], e1);
-          accumulate_bin<NCH>(e0, dx[u], dy[u], part);
-          accumulate_bin<NCH>(e1, dx[u + 1], dy[u + 1], part);
-        }
-      }
-      if ((g0 + kBpGroup) % kBpFlush == 0 || g0 + kBpGroup >= cnt) {
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          acc[c] += (double)part[c];
-          part[c] = 0.0f;
-        }
-      }
-    }
-  }
-  __syncthreads();  // every wave is done with the staging slots, which epilogues reuse
-}
-
 // Global-to-LDS copies of one view's bins for the fused primal path (qS with
-// 12 floats per ray): wave su stages view j of the chunk into dst, lane sl
-// bin d0 + sl; lanes without a bin copy the plan's zero record.
+// 12 floats per ray): wave su stages view j into dst, lane sl bin d0 + sl;
+// lanes without a bin copy the plan's zero record.
 __device__ __forceinline__ void copy_group_view(const ScanDesc &sd, const float *__restrict__ qS, unsigned nb,
-                                                const BpShared &sh, int vc, int j, int cnt, int su, int sl,
+                                                const TileBins &tb, int j, bool valid, int su, int sl,
                                                 BpSoa &dst) {
-  const ViewTile vt = sh.vt[min(j, cnt - 1)];
-  const bool has = j < cnt && sl < min(vt.nst, kBpSlot);
-  const unsigned l = (unsigned)(vc + j) * nb + (unsigned)(vt.d0 + sl);  // used only if has
-  const float4 *ra = has ? reinterpret_cast<const float4 *>(sd.rays + l) : sd.zero;
-  const float4 *qa = has ? reinterpret_cast<const float4 *>(qS) + 3 * (size_t)l : sd.zero;
+  const bool has = valid && sl < min(tb.nst, kBpSlot);
+  const unsigned l0 = (unsigned)j * nb + (unsigned)tb.d0;  // uniform
+  const float4 *ra = has ? reinterpret_cast<const float4 *>(sd.rays + l0) + 2 * sl : sd.zero;
+  const float4 *qa = has ? reinterpret_cast<const float4 *>(qS) + 3 * ((size_t)l0 + sl) : sd.zero;
   __builtin_amdgcn_global_load_lds(ra, (void OSSCIR_LDS *)&dst.a[su][0], 16, 0, 0);
   __builtin_amdgcn_global_load_lds(qa, (void OSSCIR_LDS *)&dst.b[su][0], 16, 0, 0);
   __builtin_amdgcn_global_load_lds(qa + 1, (void OSSCIR_LDS *)&dst.c[su][0], 16, 0, 0);
@@ -486,89 +392,120 @@ __device__ __forceinline__ void load_soa(const BpSoa &S, int u, int idx, BinLDS 
   if (NCH > 4) e.w2 = S.c[u][idx];
 }
 
-// The common path of the fused primal step: as back_accumulate_grouped, with
-// the next group's bins copied straight into the other LDS buffer while the
-// current group is summed (one barrier per group).  Same records, windows
-// and summation order, so the same bits.
-template <int NCH>
-__device__ __forceinline__ void back_accumulate_grouped_lds(const ScanDesc &sd, int tile_x, int tile_y,
-                                                            const float *__restrict__ qS, double acc[NCH],
-                                                            BpShared &sh) {
+// Common path (every tile shadow within kBpSlot - 2 bins; the plan checks):
+// views are staged four at a time, one wave per view, and each pixel sums
+// the group's views in pairs, a pair reading the window length of its
+// longer view.  COPY: the bins go from memory straight into double-buffered
+// LDS arrays (global-to-LDS copies, one barrier per group); otherwise they
+// are staged through registers into 80-byte records (two barriers per
+// group).  Both stagings hold the same records and sum them in the same
+// order, so they give the same bits.
+template <int NCH, bool QS12, bool COPY>
+__device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int tile_x, int tile_y,
+                                                        const float *__restrict__ q, int q_stride_i, double acc[NCH],
+                                                        BpShared &sh) {
+  static_assert(QS12 || !COPY, "global-to-LDS staging reads qS");
+  static_assert(kBpGroup == 4 && kBpGroup * 64 == kBpThreads && kBpSlot == 64, "one wave per view, one lane per bin");
+  static_assert(kBpFlush % kBpGroup == 0, "flushes at group ends");
   const int tid = threadIdx.x;
   int tx, ty;
   bp_pixel_of_thread(tid, tx, ty);
   const int ix = tile_x * kBpTile + tx;
   const int iy = tile_y * kBpTile + ty;
   const int V = sd.n_views;
-  const unsigned nb = (unsigned)sd.n_bins;
-  const float X = (float)ix - sd.c0;
+  const int nt = (sd.n + kBpTile - 1) / kBpTile;
+  const unsigned nb = (unsigned)sd.n_bins, q_stride = (unsigned)q_stride_i;
+  const float X = (float)ix - sd.c0;  // centred, for the detector projection
   const float Y = (float)iy - sd.c0;
   const float sid = in_vgpr(sd.sid_px);
   const double fx = (double)ix, fy = (double)iy;
-  const int su = tid >> 6, sl = tid & 63;
-  static_assert(kBpGroup * 64 == kBpThreads && kBpSlot == 64, "one wave per view, one lane per bin");
-  static_assert(kBpViewChunk % kBpFlush == 0 && kBpFlush % kBpGroup == 0, "flushes at group ends");
+  const int su = __builtin_amdgcn_readfirstlane(tid >> 6), sl = tid & 63;  // staged slot: view su, bin sl
+  const TileBins *__restrict__ tbs = sd.tile_bins + (size_t)(tile_y * nt + tile_x) * V;
 #pragma unroll
   for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
-  for (int vc = 0; vc < V; vc += kBpViewChunk) {
-    const int cnt = min(kBpViewChunk, V - vc);
-    __syncthreads();  // the previous chunk is done with sh
-    if (tid < cnt) tile_view_bounds(sd, sd.views[vc + tid], tile_x, tile_y, sh.vt[tid]);
-    __syncthreads();
-    copy_group_view(sd, qS, nb, sh, vc, su, cnt, su, sl, sh.soa[0]);
-    float part[NCH];
+  float part[NCH];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) part[c] = 0.0f;
-    int buf = 0;
-    for (int g0 = 0; g0 < cnt; g0 += kBpGroup) {
+  for (int c = 0; c < NCH; ++c) part[c] = 0.0f;
+  BinRegs<NCH> nxt;
+  {
+    const TileBins tb = load_uniform(tbs + min(su, V - 1));
+    if (COPY)
+      copy_group_view(sd, q, nb, tb, su, su < V, su, sl, sh.soa[0]);
+    else
+      group_load<NCH, QS12>(sd, q, q_stride, nb, tb, su, su < V, sl, nxt);
+  }
+  int buf = 0;
+  for (int g0 = 0; g0 < V; g0 += kBpGroup) {
+    if (COPY) {
       __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of the group have landed
       __syncthreads();                // every wave's have; the other buffer's reads are done
-      if (g0 + kBpGroup < cnt) copy_group_view(sd, qS, nb, sh, vc, g0 + kBpGroup + su, cnt, su, sl, sh.soa[buf ^ 1]);
-      const BpSoa &S = sh.soa[buf];
-      ViewTile vt[kBpGroup];
-      ViewGeom vg[kBpGroup];
-#pragma unroll
-      for (int u = 0; u < kBpGroup; ++u) {
-        const int j = min(g0 + u, cnt - 1);
-        vt[u] = sh.vt[j];
-        vg[u] = load_uniform(sd.views + vc + j);
+      const int jn = g0 + kBpGroup + su;
+      if (g0 + kBpGroup < V) {
+        const TileBins tb = load_uniform(tbs + min(jn, V - 1));
+        copy_group_view(sd, q, nb, tb, jn, jn < V, su, sl, sh.soa[buf ^ 1]);
       }
-      float t[kBpGroup];
-      int nst[kBpGroup], s[kBpGroup];
-      double dx[kBpGroup], dy[kBpGroup];
-      int kmax = 0;
-#pragma unroll
-      for (int u = 0; u < kBpGroup; ++u) {
-        nst[u] = g0 + u < cnt ? min(__builtin_amdgcn_readfirstlane(vt[u].nst), kBpSlot) : 0;
-        kmax = max(kmax, min(__builtin_amdgcn_readfirstlane(vt[u].K), nst[u]));
-        const float num = __fmaf_rn(vg[u].cb, Y, -vg[u].sb * X);
-        const float den = __fmaf_rn(-vg[u].sb, Y, __fmaf_rn(-vg[u].cb, X, sid));
-        t[u] = __fmaf_rn(num * __builtin_amdgcn_rcpf(den), sd.bin_scale, vt[u].off);
-        dx[u] = vg[u].sx - fx;
-        dy[u] = vg[u].sy - fy;
-      }
-#pragma unroll
-      for (int u = 0; u < kBpGroup; ++u) s[u] = clamp_0_hi(floor_to_int(t[u]), max(0, nst[u] - kmax));
-      const int kmx = __builtin_amdgcn_readfirstlane(kmax);
-      for (int i = 0; i < kmx; ++i) {
-#pragma unroll
-        for (int u = 0; u < kBpGroup; u += 2) {
-          BinLDS e0, e1;
-          load_soa<NCH>(S, u, s[u] + i, e0);
-          load_soa<NCH>(S, u + 1, s[u + 1] + i, e1);
-          accumulate_bin<NCH>(e0, dx[u], dy[u], part);
-          accumulate_bin<NCH>(e1, dx[u + 1], dy[u + 1], part);
-        }
-      }
-      if ((g0 + kBpGroup) % kBpFlush == 0 || g0 + kBpGroup >= cnt) {
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          acc[c] += (double)part[c];
-          part[c] = 0.0f;
-        }
-      }
-      buf ^= 1;
+    } else {
+      __syncthreads();  // the previous group's windows have been read
+      bin_store<NCH>(nxt, sh.gbins[su][sl]);
+      __syncthreads();
+      const int jn = g0 + kBpGroup + su;
+      const TileBins tb = load_uniform(tbs + min(jn, V - 1));
+      group_load<NCH, QS12>(sd, q, q_stride, nb, tb, jn, jn < V, sl, nxt);
     }
+    // the group's views (views past the last one have no staged bins)
+    int K[kBpGroup], nst[kBpGroup];
+    float t[kBpGroup];
+    double dx[kBpGroup], dy[kBpGroup];
+#pragma unroll
+    for (int u = 0; u < kBpGroup; ++u) {
+      const int j = min(g0 + u, V - 1);
+      const TileBins tb = load_uniform(tbs + j);
+      const ViewGeom vg = load_uniform(sd.views + j);
+      nst[u] = g0 + u < V ? min(tb.nst, kBpSlot) : 0;
+      K[u] = min(tb.K, nst[u]);
+      const float num = __fmaf_rn(vg.cb, Y, -vg.sb * X);
+      const float den = __fmaf_rn(-vg.sb, Y, __fmaf_rn(-vg.cb, X, sid));
+      t[u] = __fmaf_rn(num * __builtin_amdgcn_rcpf(den), sd.bin_scale, tb.off);
+      dx[u] = vg.sx - fx;
+      dy[u] = vg.sy - fy;
+    }
+#pragma unroll
+    for (int p = 0; p < kBpGroup; p += 2) {
+      // window u: [s, s + kp) inside [0, max(nst, kp)) within the slot,
+      // starting at floor(tau - hw) + 1: it covers the staged part of the
+      // pixel's shadow, the integers inside (tau - hw, tau + hw) (at most
+      // K <= kp of them); slots past nst hold zero records
+      const int kp = max(K[p], K[p + 1]);  // uniform
+      const int s0 = clamp_0_hi(floor_to_int(t[p]), max(0, nst[p] - kp));
+      const int s1 = clamp_0_hi(floor_to_int(t[p + 1]), max(0, nst[p + 1] - kp));
+      if (COPY) {
+        const BpSoa &S = sh.soa[buf];
+        for (int i = 0; i < kp; ++i) {
+          BinLDS e0, e1;  // two views' reads in flight before the first weight
+          load_soa<NCH>(S, p, s0 + i, e0);
+          load_soa<NCH>(S, p + 1, s1 + i, e1);
+          accumulate_bin<NCH>(e0, dx[p], dy[p], part);
+          accumulate_bin<NCH>(e1, dx[p + 1], dy[p + 1], part);
+        }
+      } else {
+        const BinLDS *w0 = &sh.gbins[p][s0], *w1 = &sh.gbins[p + 1][s1];
+        for (int i = 0; i < kp; ++i) {
+          BinLDS e0, e1;
+          load_bin<NCH>(w0[i], e0);
+          load_bin<NCH>(w1[i], e1);
+          accumulate_bin<NCH>(e0, dx[p], dy[p], part);
+          accumulate_bin<NCH>(e1, dx[p + 1], dy[p + 1], part);
+        }
+      }
+    }
+    if ((g0 + kBpGroup) % kBpFlush == 0 || g0 + kBpGroup >= V) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        acc[c] += (double)part[c];
+        part[c] = 0.0f;
+      }
+    }
+    buf ^= 1;
   }
   __syncthreads();  // every wave is done with the staging buffers, which epilogues reuse
 }
@@ -584,10 +521,8 @@ __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, 
   static_assert(QS12 || !COPY, "global-to-LDS staging reads qS");
   if (WIDE)
     back_accumulate_views<NCH, QS12>(sd, tile_x, tile_y, q, q_stride_i, acc, sh);
-  else if (COPY)
-    back_accumulate_grouped_lds<NCH>(sd, tile_x, tile_y, q, acc, sh);
   else
-    back_accumulate_grouped<NCH, QS12>(sd, tile_x, tile_y, q, q_stride_i, acc, sh);
+    back_accumulate_grouped<NCH, QS12, COPY>(sd, tile_x, tile_y, q, q_stride_i, acc, sh);
 }
 
 }  // namespace osscir

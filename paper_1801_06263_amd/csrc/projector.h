@@ -24,6 +24,11 @@ hipError_t launch_pack(const ScanDesc &sd, const float *f, int nch, void *pack, 
 // b[c][k] = sum_l X_{l,k} q[c][l] (chunks of 9, 6, 3, 2 or 1 channels).
 hipError_t launch_back(const ScanDesc &sd, const float *q, int nch, float *b, hipStream_t st);
 
+// The common back-projection path's staged bins of every (tile, view):
+// tile_bins_count(sd) entries, tiles row-major, views fastest (plan setup).
+size_t tile_bins_count(const ScanDesc &sd);
+hipError_t launch_tile_bins(const ScanDesc &sd, TileBins *out, hipStream_t st);
+
 // Workgroups of the tile-driven back-projection kernels (all tiles of the
 // image in ScanDesc::tile_order, XCD-partitioned).
 unsigned back_blocks(const ScanDesc &sd);

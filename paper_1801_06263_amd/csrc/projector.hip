@@ -42,6 +42,20 @@ __global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__re
                       (float4 OSSCIR_LDS *)fwd_lds[threadIdx.x >> 6]);
 }
 
+// ----------------------------------------------------------------- plan
+
+// The staged bins of every (tile, view) of the common back-projection path:
+// one thread per pair, tiles in row-major order, views fastest.
+__global__ void __launch_bounds__(256) k_tile_bins(ScanDesc sd, TileBins *__restrict__ out) {
+  const int nt = (sd.n + kBpTile - 1) / kBpTile;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)nt * nt * sd.n_views) return;
+  const int v = (int)(i % sd.n_views), t = (int)(i / sd.n_views);
+  ViewTile vt;
+  tile_view_bounds(sd, sd.views[v], t % nt, t / nt, vt);
+  out[i] = TileBins{vt.d0, vt.nst, vt.K, vt.off};
+}
+
 // ----------------------------------------------------------------- back
 
 template <int NCH, bool WIDE>
@@ -116,6 +130,17 @@ hipError_t launch_count(const ScanDesc &sd, int *nnz, hipStream_t st) {
   const dim3 fgrid(forward_blocks(sd));
   hipLaunchKernelGGL(k_forward<true>, fgrid, dim3(kFpBlock), 0, st, sd, nullptr, nullptr, reinterpret_cast<float *>(nnz),
                      0, 1);
+  return hipGetLastError();
+}
+
+size_t tile_bins_count(const ScanDesc &sd) {
+  const size_t nt = (size_t)(sd.n + kBpTile - 1) / kBpTile;
+  return nt * nt * (size_t)sd.n_views;
+}
+
+hipError_t launch_tile_bins(const ScanDesc &sd, TileBins *out, hipStream_t st) {
+  const size_t count = tile_bins_count(sd);
+  hipLaunchKernelGGL(k_tile_bins, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, sd, out);
   return hipGetLastError();
 }
 

@@ -62,11 +62,13 @@ def spectral_key(spec) -> str:
 
 
 def plan_bytes(geom) -> int:
-    """Device bytes a plan holds: ray lines (24 B) and rho (4 B) per ray,
-    views, the projector scratch and the spectral table (small)."""
+    """Device bytes a plan holds: ray lines (32 B) and rho (4 B) per ray,
+    views, the projector scratch, the back-projector's staged bins per
+    (16 x 16 tile, view) (16 B) and the spectral table (small)."""
     L = geom.n_views * geom.n_bins
     np_ = geom.n + 8
-    return 28 * L + 24 * geom.n_views + 32 * np_ * np_ + 512 * 48 * 4
+    nt = (geom.n + 15) // 16
+    return 36 * L + 32 * geom.n_views + 32 * np_ * np_ + 16 * nt * nt * geom.n_views + 512 * 48 * 4
 
 
 def request_bytes(geom, workspace_bytes: int) -> int:
