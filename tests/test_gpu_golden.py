@@ -1,7 +1,11 @@
-"""MOCCA trajectory parity on the 256^2 / 256 views x 512 bins / 100-energy
-workload against the stored FP64 oracle run (tests/golden/make_golden.py):
-maps after 100 iterations within 1e-3 relative L2 per material, and the
-D_TPL history every 10 iterations."""
+"""MOCCA trajectory parity against stored FP64 oracle runs
+(tests/golden/make_golden.py): maps after 100 iterations within 1e-3
+relative L2 per material, and the D_TPL history every 10 iterations.
+
+  medium: 256^2 / 256 views x 512 bins / 100 energies, lambda 3e-7
+  large:  512^2 / 720 views x 1024 bins / 120 energies, lambda 2e-8, the
+          benchmark's scan and launch configuration (the stored counts are
+          the oracle's Poisson draw at the phantom)"""
 import os
 import sys
 import warnings
@@ -9,6 +13,7 @@ import warnings
 import numpy as np
 import pytest
 
+import synth
 from helpers import dev, host, sino
 
 warnings.filterwarnings("ignore", category=RuntimeWarning)
@@ -25,22 +30,54 @@ def medium():
     from paper_1801_06263_amd import Plan
     pr, X, c = make_golden.medium_inputs()
     gold = np.load(os.path.join(HERE, "golden", "medium_block_clip.npz"))
-    return pr, c, gold, Plan(pr.geom, pr.spec), make_golden.MEDIUM
+    return pr, dev(sino(c, pr.geom.n_views, pr.geom.n_bins)), gold, Plan(pr.geom, pr.spec), make_golden.MEDIUM
 
 
-@pytest.mark.parametrize("fp64", [False, True])
-def test_medium_trajectory_matches_oracle(medium, fp64):
+@pytest.fixture(scope="module")
+def large():
+    import make_golden
+    from paper_1801_06263_amd import Plan
+    pr = synth.problem("large")
+    gold = np.load(os.path.join(HERE, "golden", "large_block_clip.npz"))
+    c = dev(gold["counts"].astype(np.float32))
+    return pr, c, gold, Plan(pr.geom, pr.spec), make_golden.LARGE
+
+
+def check_trajectory(case, fp64):
     from paper_1801_06263_amd import Params
-    pr, c, gold, plan, cfg = medium
-    g = pr.geom
-    st = plan.new_state(dev(sino(c, g.n_views, g.n_bins)))
+    pr, c, gold, plan, cfg = case
+    st = plan.new_state(c)
     hist = host(plan.mocca_iterate(st, Params(cfg["lam"], cfg["precond"], cfg["curvature"], fp64), cfg["n_iter"],
                                    dtpl=True))
     f = host(st.f)
     ref = gold["f"].astype(np.float64)
+    rels = []
     for m in range(3):
         rel = np.linalg.norm(f[m] - ref[m]) / np.linalg.norm(ref[m])
-        print(f"fp64_small={fp64} material {m}: rel L2 {rel:.2e}")
-        assert rel <= 1e-3
+        print(f"{cfg['name']} fp64_small={fp64} material {m}: rel L2 {rel:.2e}")
+        rels.append(rel)
     d = hist[gold["iters"] - 1]
-    np.testing.assert_allclose(d, gold["dtpl"], rtol=1e-3)
+    print(f"{cfg['name']} fp64_small={fp64} D_TPL max rel dev {np.max(np.abs(d / gold['dtpl'] - 1)):.2e}")
+    return rels, d, gold["dtpl"]
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_medium_trajectory_matches_oracle(medium, fp64):
+    rels, d, ref = check_trajectory(medium, fp64)
+    assert max(rels) <= 1e-3
+    np.testing.assert_allclose(d, ref, rtol=1e-3)
+
+
+def test_large_trajectory_matches_oracle(large):
+    """The benchmark's configuration (FP64 per-ray tail)."""
+    rels, d, ref = check_trajectory(large, True)
+    assert max(rels) <= 1e-3
+    np.testing.assert_allclose(d, ref, rtol=1e-3)
+
+
+def test_large_trajectory_fp32_tail(large):
+    """The optional FP32 per-ray tail on the benchmark's scan: reported, and
+    held to the looser bound its drift needs on the 64^2 edge-ray scan."""
+    rels, d, ref = check_trajectory(large, False)
+    assert max(rels) <= 3e-3
+    np.testing.assert_allclose(d, ref, rtol=3e-3)
