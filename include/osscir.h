@@ -82,6 +82,10 @@ typedef struct {
  * to 1) with incident photons per ray n0 [n_resp][n_win].  n_resp = 0 or 1:
  * one response shared by every ray; n_resp = n_bins: one per detector bin d
  * (the same in every view), the calibrated per-pixel spectra of Sec. III.
+ * n0_ray (optional, NULL = none): incident photons of every ray and window,
+ * [n_views][n_bins][n_win], the N_{w,l} of Eq. (fullModel) in full (for
+ * instance a tube current that varies with the view); it replaces n0 for
+ * every ray, with either kind of response.
  * Supported: n_mat = 3, n_win = 4, 1 <= n_energy <= 512. */
 typedef struct {
   int32_t n_mat, n_win, n_energy;
@@ -89,6 +93,7 @@ typedef struct {
   const double *s;
   const double *n0;
   int32_t n_resp;
+  const double *n0_ray;
 } osscir_spectral;
 
 /* Step-size ratio lambda > 0 (Sec. II: "a step size ratio parameter that must

@@ -82,6 +82,7 @@ void free_plan(osscir_plan p) {
   if (p->d_pack) (void)hipFree(p->d_pack);
   if (p->d_sbin) (void)hipFree(p->d_sbin);
   if (p->d_n0bin) (void)hipFree(p->d_n0bin);
+  if (p->d_n0ray) (void)hipFree(p->d_n0ray);
   if (p->d_tile_order) (void)hipFree(p->d_tile_order);
   if (p->d_zero) (void)hipFree(p->d_zero);
   if (p->d_tile_bins) (void)hipFree(p->d_tile_bins);
@@ -213,6 +214,10 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
     }
   for (int j = 0; j < kMat * I; ++j)
     if (!std::isfinite(spec->mu[j])) return fail(OSSCIR_EINVAL, "mu not finite");
+  if (spec->n0_ray)
+    for (size_t j = 0; j < (size_t)g.n_views * g.n_bins * kWin; ++j)
+      if (!(spec->n0_ray[j] > 0) || !std::isfinite(spec->n0_ray[j]))
+        return fail(OSSCIR_EINVAL, "n0_ray[%zu] must be > 0 and finite", j);
 
   osscir_plan p = new (std::nothrow) osscir_plan_s;
   if (!p) return fail(OSSCIR_ENOMEM, "host allocation failed");
@@ -265,6 +270,14 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
     }
   }
 
+  std::vector<float4> n0ray;
+  if (spec->n0_ray) {
+    n0ray.resize(L);
+    for (size_t l = 0; l < L; ++l) {
+      const double *n0 = spec->n0_ray + l * kWin;
+      n0ray[l] = make_float4((float)n0[0], (float)n0[1], (float)n0[2], (float)n0[3]);
+    }
+  }
   const std::vector<int> tiles = region_tile_order((N + kBpTile - 1) / kBpTile);
   hipError_t e;
   if ((e = hipMalloc(&p->d_rays, rays.size() * sizeof(RayLine))) != hipSuccess ||
@@ -274,6 +287,7 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
       (e = hipMalloc(&p->d_tab, tab.size() * sizeof(float))) != hipSuccess ||
       (per_bin && (e = hipMalloc(&p->d_sbin, sbin.size() * sizeof(float4))) != hipSuccess) ||
       (per_bin && (e = hipMalloc(&p->d_n0bin, n0bin.size() * sizeof(float4))) != hipSuccess) ||
+      (!n0ray.empty() && (e = hipMalloc(&p->d_n0ray, n0ray.size() * sizeof(float4))) != hipSuccess) ||
       (e = hipMalloc(&p->d_tile_order, tiles.size() * sizeof(int))) != hipSuccess ||
       (e = hipMalloc(&p->d_zero, 256)) != hipSuccess) {
     free_plan(p);
@@ -287,6 +301,8 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
        (e = hipMemcpy(p->d_sbin, sbin.data(), sbin.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess) ||
       (per_bin && (e = hipMemcpy(p->d_n0bin, n0bin.data(), n0bin.size() * sizeof(float4), hipMemcpyHostToDevice)) !=
                       hipSuccess) ||
+      (!n0ray.empty() &&
+       (e = hipMemcpy(p->d_n0ray, n0ray.data(), n0ray.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess) ||
       (e = hipMemcpy(p->d_tile_order, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice)) !=
           hipSuccess ||
       (e = hipMemset(p->d_zero, 0, 256)) != hipSuccess) {
@@ -310,6 +326,7 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   sd.zero = p->d_zero;
   sd.sbin = p->d_sbin;
   sd.n0bin = p->d_n0bin;
+  sd.n0ray = p->d_n0ray;
   // does any 16x16 tile's shadow exceed a staging slot of the back-projector's
   // grouped path?
   // (the same corner projection the kernel uses, in FP64 with a margin)

@@ -34,6 +34,7 @@ __device__ __forceinline__ SlotDesc load_slot(const SlotDesc *slots, int s) {
   d.sd.views = as_global(q->sd.views);
   d.sd.sbin = as_global(q->sd.sbin);
   d.sd.n0bin = as_global(q->sd.n0bin);
+  d.sd.n0ray = as_global(q->sd.n0ray);
   d.f = as_global(q->f);
   d.fbar = as_global(q->fbar);
   d.y = as_global(q->y);

@@ -81,6 +81,7 @@ struct ScanDesc {
   int mfma;          // energy sums on the matrix cores (shared table, fits LDS)
   const float4 *sbin;   // [I][D] s_{w,d,i} (w = x, y, z, w), per_bin only
   const float4 *n0bin;  // [D] incident counts per window, per_bin only
+  const float4 *n0ray;  // [L] incident counts per window of every ray (replaces n0 / n0bin), or null
   const int *tile_order;  // [nt * nt] back-projection tiles (ty * nt + tx) in region order
   const TileBins *tile_bins;  // [nt * nt][V] staged bins per (tile, view); null on the wide path
   const float4 *zero;     // 256 bytes of zeros (a null ray record and null inputs)

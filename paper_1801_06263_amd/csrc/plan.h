@@ -21,6 +21,7 @@ struct osscir_plan_s {
   float *d_tab = nullptr;
   float4 *d_sbin = nullptr;   // per-detector-bin responses [I][D]
   float4 *d_n0bin = nullptr;  // per-detector-bin incident counts [D]
+  float4 *d_n0ray = nullptr;  // per-ray incident counts [L] (optional)
   int *d_tile_order = nullptr;  // back-projection tiles in region order
   float4 *d_zero = nullptr;     // 256 zero bytes the back-projector stages for empty slots
   osscir::TileBins *d_tile_bins = nullptr;  // staged bins per (tile, view) of the common back-projection path

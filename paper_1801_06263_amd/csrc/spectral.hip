@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(256) k_spectral_model(ScanDesc sd, const float
   const int d = l % sd.n_bins;
   float g[kWin], af[kWin * kMat], hb[kWin * 6], n0[kWin];
   const float scale = energy_sums_safe<true, true, PB>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb, d);
-  ray_n0<PB>(sd, d, n0);
+  ray_n0<PB>(sd, l, d, n0);
   T a[kWin][kMat], cw[kWin], rg[kWin];
 #pragma unroll
   for (int w = 0; w < kWin; ++w) {
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) k_dtpl_partial(ScanDesc sd, const float *
     const int d = l % sd.n_bins;
     float g[kWin], n0[kWin];
     energy_sums<false, false, false, PB>(sd, p[l], p[L + l], p[2 * L + l], g, nullptr, nullptr, 0.0f, d);
-    ray_n0<PB>(sd, d, n0);
+    ray_n0<PB>(sd, l, d, n0);
 #pragma unroll
     for (int w = 0; w < kWin; ++w) {
       const double ch = (double)n0[w] * (double)g[w];

@@ -255,10 +255,17 @@ __device__ __forceinline__ void energy_sums_mfma(const ScanDesc &sd, float *stab
   }
 }
 
-// Incident counts of window w on the ray of detector bin d.
+// Incident counts of window w on ray l (detector bin d): the plan's per-ray
+// table if it has one, else per detector bin (PB) or shared.
 template <bool PB>
-__device__ __forceinline__ void ray_n0(const ScanDesc &sd, int d, float n0[kWin]) {
-  if (PB) {
+__device__ __forceinline__ void ray_n0(const ScanDesc &sd, int l, int d, float n0[kWin]) {
+  if (sd.n0ray) {  // uniform
+    const float4 v = sd.n0ray[l];
+    n0[0] = v.x;
+    n0[1] = v.y;
+    n0[2] = v.z;
+    n0[3] = v.w;
+  } else if (PB) {
     const float4 v = sd.n0bin[d];
     n0[0] = v.x;
     n0[1] = v.y;
@@ -321,7 +328,7 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
   const int d = l % sd.n_bins;
   const float scale = MFMA ? energy_sums_rescue<true, CLIP, PB>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb, d)
                            : energy_sums_safe<true, CLIP, PB>(sd, p[l], p[L + l], p[2 * L + l], g, af, hb, d);
-  ray_n0<PB>(sd, d, n0);
+  ray_n0<PB>(sd, l, d, n0);
 
   T a[kWin][kMat], cw[kWin], rw[kWin], yw[kWin], sig[kWin], ig[kWin];
 #pragma unroll

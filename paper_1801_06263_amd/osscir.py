@@ -32,7 +32,7 @@ class _Geometry(ctypes.Structure):
 
 class _Spectral(ctypes.Structure):
     _fields_ = [("n_mat", c_int32), ("n_win", c_int32), ("n_energy", c_int32),
-                ("mu", _dp), ("s", _dp), ("n0", _dp), ("n_resp", c_int32)]
+                ("mu", _dp), ("s", _dp), ("n0", _dp), ("n_resp", c_int32), ("n0_ray", _dp)]
 
 
 class _Params(ctypes.Structure):
@@ -175,13 +175,18 @@ class Plan:
         g = _c_geometry(geom)
         self._mu = np.ascontiguousarray(spec.mu, dtype=np.float64)
         self._s = np.ascontiguousarray(spec.s, dtype=np.float64)
-        self._n0 = np.ascontiguousarray(spec.n0, dtype=np.float64)
-        # s [W, I] shared by every ray, or [D, W, I] per detector bin
+        # s [W, I] shared by every ray, or [D, W, I] per detector bin; incident
+        # counts n0 [W] or [D, W], and optionally per ray: n0_ray [V, D, W]
+        n0_ray = getattr(spec, "n0_ray", None)
+        self._n0 = np.ascontiguousarray(spec.n0_nominal if n0_ray is not None else spec.n0, dtype=np.float64)
+        self._n0_ray = None
+        if n0_ray is not None:
+            self._n0_ray = np.ascontiguousarray(n0_ray, dtype=np.float64).reshape(self.n_views, self.n_bins, -1)
         n_resp = self._s.shape[0] if self._s.ndim == 3 else 1
         self.per_bin = self._s.ndim == 3
         sp = _Spectral(self._mu.shape[0], self._s.shape[-2], self._s.shape[-1],
                        self._mu.ctypes.data_as(_dp), self._s.ctypes.data_as(_dp), self._n0.ctypes.data_as(_dp),
-                       n_resp)
+                       n_resp, self._n0_ray.ctypes.data_as(_dp) if self._n0_ray is not None else None)
         h = c_void_p()
         _check(lib.osscir_plan_create(ctypes.byref(g), ctypes.byref(sp), ctypes.byref(h)))
         self._h = h
@@ -365,7 +370,7 @@ def mu_pc_basis(spec):
     if s.ndim != 2:
         raise ValueError("mu-PC needs one shared window response s [W, I]")
     sp = _Spectral(mu.shape[0], s.shape[0], s.shape[1], mu.ctypes.data_as(_dp), s.ctypes.data_as(_dp),
-                   n0.ctypes.data_as(_dp), 1)
+                   n0.ctypes.data_as(_dp), 1, None)
     B = np.zeros((3, 3))
     mu_t = np.zeros_like(mu)
     _check(lib.osscir_mu_pc_basis(ctypes.byref(sp), B.ctypes.data_as(_dp), mu_t.ctypes.data_as(_dp)))

@@ -235,6 +235,59 @@ def make_detector_spectral(n_bins: int, e_lo: int, e_hi: int, kvp: float, i0: fl
     return DetectorSpectral(mu=attenuation_table(energies), s=s, n0=n0)
 
 
+@dataclasses.dataclass(frozen=True)
+class ModulatedSpectral:
+    """Window responses (shared [W][I] or per detector bin [D][W][I]) with
+    incident counts that vary from ray to ray: n0 [L][W] (the N_{w,l} of
+    Eq. fullModel in full), n0_nominal the counts without modulation ([W] or
+    [D][W])."""
+    mu: np.ndarray
+    s: np.ndarray
+    n0: np.ndarray
+    n0_nominal: np.ndarray
+
+    @property
+    def n0_ray(self) -> np.ndarray:
+        return self.n0
+
+    @property
+    def n_mat(self) -> int:
+        return self.mu.shape[0]
+
+    @property
+    def n_win(self) -> int:
+        return self.s.shape[-2]
+
+    @property
+    def n_energy(self) -> int:
+        return self.s.shape[-1]
+
+
+def tube_modulation(geom: Geometry, depth: float = 0.3, bowtie: float = 0.25, seed: int = 0) -> np.ndarray:
+    """Relative incident intensity of every ray, [L] (view-major): a tube
+    current modulated with the view angle, 1 + depth cos(2 beta + phase) (as
+    for an elliptical patient), times a bowtie filter that attenuates the fan
+    towards its edges, 1 - bowtie (u / u_max)^2, times 1% ray-to-ray jitter
+    from PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    beta = geom.view0_rad + geom.arc_rad * np.arange(geom.n_views) / geom.n_views
+    phase = rng.uniform(0.0, 2.0 * math.pi)
+    tube = 1.0 + depth * np.cos(2.0 * beta + phase)
+    u = (np.arange(geom.n_bins) - 0.5 * (geom.n_bins - 1)) / (0.5 * max(geom.n_bins - 1, 1))
+    bow = 1.0 - bowtie * u ** 2
+    jitter = 1.0 + 0.01 * rng.standard_normal((geom.n_views, geom.n_bins))
+    return (tube[:, None] * bow[None, :] * jitter).reshape(-1)
+
+
+def modulated_spectral(spec, geom: Geometry, seed: int = 0, **kw) -> ModulatedSpectral:
+    """spec (Spectral or DetectorSpectral) with its incident counts scaled
+    per ray by tube_modulation (the same factor in every window)."""
+    rel = tube_modulation(geom, seed=seed, **kw)
+    n0 = np.asarray(spec.n0, dtype=np.float64)
+    base = np.tile(n0, (geom.n_views, 1)) if n0.ndim == 2 else np.broadcast_to(n0, (rel.size, n0.size))
+    return ModulatedSpectral(mu=spec.mu, s=spec.s, n0=base * rel[:, None], n0_nominal=n0)
+
+
 # ----------------------------------------------------------------- phantom
 
 def disk_phantom(n: int, fov_cm: float, disks: List[Tuple[float, float, float, Tuple[float, float, float]]],

@@ -518,3 +518,87 @@ def test_detector_spectra_in_a_batch(tiny_det):
     plan_s.mocca_iterate(r1, Params(3e-7, "block", "clip", True), 6)
     assert torch.equal(s0.f, r0.f) and torch.equal(s0.y, r0.y)
     assert torch.equal(s1.f, r1.f) and torch.equal(s1.y, r1.y)
+
+
+# ---------------------------------------------------------------- per-ray incident counts
+
+@pytest.fixture(scope="module")
+def tiny_mod():
+    """The tiny scan with a view-dependent tube current and a bowtie: one
+    incident count per ray and window, shared window responses."""
+    pr = synth.problem("tiny")
+    X = pj.system_matrix(pr.geom)
+    ms = synth.modulated_spectral(pr.spec, pr.geom, seed=21)
+    c = synth.poisson_counts(model.counts_model(X @ pr.f_true.reshape(3, -1).T, ms), pr.seed)
+    return pr, ms, X, c, plan_for(pr.geom, ms)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_per_ray_incident_spectral_model_parity(tiny_mod, fp64):
+    pr, ms, X, c, plan = tiny_mod
+    rng = np.random.default_rng(17)
+    f = pr.f_true.reshape(3, -1) * (1.3 + 0.2 * rng.standard_normal((3, X.shape[1])))
+    p32 = (X @ f.T).astype(np.float32)
+    out = plan.spectral_model(dev(sino(p32, pr.geom)), dev(sino(c, pr.geom)), fp64_small=fp64)
+    p = p32.astype(np.float64)
+    A, B, g = model.matrices_AB(p, ms)
+    chat = ms.n0 * g
+    H = model.hessian_from_AB(A, B, g, c, ms)
+    assert normwise(host(out["chat"]), sino(chat, pr.geom)) <= 1e-5
+    assert normwise(host(out["r"]), sino(c - chat, pr.geom)) <= 1e-5
+    Hg = host(out["H"]).reshape(6, -1)
+    for j, (m, n) in enumerate([(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]):
+        assert np.abs(Hg[j] - H[:, m, n]).max() <= 1e-4 * np.abs(H).max()
+    z = plan.spectral_model(torch.zeros(3, pr.geom.n_views, pr.geom.n_bins, device="cuda"), dev(sino(c, pr.geom)))
+    np.testing.assert_allclose(host(z["chat"]), sino(ms.n0, pr.geom), rtol=2e-6)
+
+
+def test_per_ray_incident_trajectory_and_dtpl(tiny_mod):
+    """100 iterations (matrix-core energy sums: the response is shared) and
+    D_TPL against the oracle."""
+    from paper_1801_06263_amd import Params
+    pr, ms, X, c, plan = tiny_mod
+    lam, n_it = 3e-7, 100
+    ref, _ = omocca.mocca(X, c, ms, lam, n_it, "block", "clip")
+    st = plan.new_state(dev(sino(c, pr.geom)))
+    plan.mocca_iterate(st, Params(lam, "block", "clip", True), n_it)
+    f = host(st.f).reshape(3, -1)
+    for m in range(3):
+        rel = np.linalg.norm(f[m] - ref.f[m]) / np.linalg.norm(ref.f[m])
+        print(f"per-ray incident counts, material {m}: rel L2 {rel:.2e}")
+        assert rel <= 1e-3
+    d = float(plan.dtpl(dev(f.reshape(3, pr.geom.n, pr.geom.n)), st.c).item())
+    d_ref = model.image_objective(X, f.astype(np.float32).astype(np.float64), c, ms)
+    assert abs(d - d_ref) <= 1e-4 * abs(d_ref)
+
+
+def test_per_ray_incident_with_per_bin_responses(tiny_det):
+    """Per-detector-bin responses and per-ray incident counts together."""
+    pr, det, rs, X, c, _ = tiny_det
+    md = synth.modulated_spectral(det, pr.geom, seed=22)
+    plan = plan_for(pr.geom, md)
+    assert plan.per_bin
+    rr = synth.RaySpectral(mu=det.mu, s=rs.s, n0=md.n0)
+    rng = np.random.default_rng(18)
+    f = pr.f_true.reshape(3, -1) * (1.2 + 0.2 * rng.standard_normal((3, X.shape[1])))
+    p32 = (X @ f.T).astype(np.float32)
+    out = plan.spectral_model(dev(sino(p32, pr.geom)), dev(sino(c, pr.geom)), fp64_small=True)
+    A, B, g = model.matrices_AB(p32.astype(np.float64), rr)
+    assert normwise(host(out["chat"]), sino(md.n0 * g, pr.geom)) <= 1e-5
+    G = model.ray_jacobian_from_A(A, rr)
+    Gs = np.stack([G[:, w, m] for w in range(4) for m in range(3)])
+    for j in range(12):
+        assert normwise(host(out["G"])[j].ravel(), Gs[j]) <= 1e-5
+
+
+def test_per_ray_incident_in_a_batch(tiny_mod):
+    from paper_1801_06263_amd import Batch, Params
+    pr, ms, X, c, plan = tiny_mod
+    cd = dev(sino(c, pr.geom))
+    b = Batch(Params(1.0, "block", "clip", True), 3)
+    s = plan.new_state(cd)
+    b.set_slot(2, plan, s, 3e-7)
+    b.iterate(5)
+    r = plan.new_state(cd)
+    plan.mocca_iterate(r, Params(3e-7, "block", "clip", True), 5)
+    assert torch.equal(s.f, r.f) and torch.equal(s.y, r.y)

@@ -736,3 +736,25 @@ def test_smoke_configuration_converges():
     assert np.isfinite(st.f).all()
     d = [h[1] for h in hist]
     assert d[-1] < d[0] and d[-1] < 1e-2 * model.image_objective(X, np.zeros((3, 32 * 32)), c, spec)
+
+
+def test_per_ray_incident_counts_with_a_shared_response():
+    """Incident counts per ray (view-dependent) with one shared response:
+    zero attenuation gives chat = N_{w,l} exactly, and every quantity equals
+    the fully per-ray tables with the response repeated."""
+    geom, spec, f_true = micro_problem()
+    X = pj.system_matrix(geom)
+    L = X.shape[0]
+    ms = synth.modulated_spectral(spec, geom, seed=9)
+    assert ms.n0.shape == (L, 4) and np.ptp(ms.n0[:, 0]) > 0.3 * spec.n0[0]
+    np.testing.assert_allclose(model.counts_model(np.zeros((L, 3)), ms), ms.n0, rtol=1e-15)
+    rs = synth.RaySpectral(mu=spec.mu, s=np.tile(spec.s, (L, 1, 1)), n0=ms.n0)
+    rng = np.random.default_rng(8)
+    p = X @ (f_true.reshape(3, -1) * (1 + 0.1 * rng.standard_normal((3, X.shape[1])))).T
+    c = model.counts_model(p, ms) * 1.02
+    np.testing.assert_allclose(model.counts_model(p, ms), model.counts_model(p, rs), rtol=1e-13)
+    np.testing.assert_allclose(model.hessian_p(p, c, ms), model.hessian_p(p, c, rs), rtol=1e-11,
+                               atol=1e-11 * np.abs(model.hessian_p(p, c, rs)).max())
+    st_m, _ = mocca.mocca(X, c, ms, 2e-7, 5, "block", "clip")
+    st_r, _ = mocca.mocca(X, c, rs, 2e-7, 5, "block", "clip")
+    np.testing.assert_allclose(st_m.f, st_r.f, atol=1e-10 * np.abs(st_r.f).max())
