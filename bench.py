@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--precond", default="block", choices=["block", "diag"])
     ap.add_argument("--curvature", default="clip", choices=["clip", "window"])
     ap.add_argument("--fp64-small", type=int, default=1)
+    ap.add_argument("--energy-sums", default="auto", choices=["auto", "vector"],
+                    help="vector: the spectral step's energy sums as per-ray vector FMAs instead of the "
+                         "matrix-core contraction the plan picks where it applies")
     ap.add_argument("--lam", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3, help="whole oracle iterations timed for the CPU baseline")
@@ -426,6 +429,8 @@ def main():
     lam = args.lam if args.lam is not None else DEFAULT_LAM[args.workload]
     t_setup = time.perf_counter()
     plan = Plan(geom, pr.spec)
+    if args.energy_sums == "vector":
+        plan.set_energy_sums(False)
     V, D, N = geom.n_views, geom.n_bins, geom.n
     L = V * D
     # synthetic measured counts from the library's own counts model at the phantom
@@ -527,7 +532,7 @@ def main():
         "config": {"workload": f"{args.workload}: {N}^2 maps x3 materials, fan beam {V} views x {D} bins, "
                                f"{I} energies, 4 overlapping windows",
                    "precond": args.precond, "curvature": args.curvature, "lambda": lam,
-                   "fp64_small": bool(args.fp64_small), "nnz_X": nnz},
+                   "fp64_small": bool(args.fp64_small), "energy_sums": args.energy_sums, "nnz_X": nnz},
         "projector": {"fp_grays_s": round(L / (fp_ms * 1e-3) / 1e9, 3), "fp_ms_3ch": round(fp_ms, 4),
                       "bp_grays_s": round(L / (bp_ms * 1e-3) / 1e9, 3), "bp_ms_9ch": round(bp_ms, 4)},
         "stages_ms": {KERNEL_NAMES[s]: round(stage_ms[s], 4) for s in range(3)},

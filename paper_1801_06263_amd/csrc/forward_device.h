@@ -183,6 +183,11 @@ __device__ __forceinline__ void forward_walk_lds(int lo, int hi, int n, const fl
                                                  double s_v, float slope, float base, const RayLine &ray, double &s0,
                                                  double &s1, double &s2, float4 OSSCIR_LDS *wb) {
   static_assert(kFpUnroll == 4, "the step window is bounded at its first and last column");
+  // A wave whose rays all miss the image has an empty walk range (its lo may
+  // lie far past the image): nothing to walk or copy.  Otherwise
+  // 0 <= lo <= hi <= n - 1, and every copied column (at most
+  // hi + kFpUnroll - 1 + kPad) and row (1 .. n + 6) lies inside the padded image.
+  if (lo > hi) return;
   const int np = n + 2 * kPad;
   const int lane = (int)__lane_id();
   float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
