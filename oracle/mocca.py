@@ -36,6 +36,11 @@ data; block SPC is rotation equivariant; the monochromatic case converges to
 Beer-Lambert's closed form; D_TPL descends.  The expansion point (fbar_n,
 which the paper leaves unstated) is a reading; the dense cross-check holds
 the oracle to it.
+
+``mocca_nested`` runs several such fixed-quadratic steps per expansion
+point; one outer iteration with many inner ones converges to the closed-form
+minimiser of the quadratic at that point, and one inner step per outer
+iteration is ``mocca`` bit for bit.
 """
 from __future__ import annotations
 
@@ -186,3 +191,28 @@ def mocca(X, c, spec, lam: float, n_iter: int, precond: str = "block", curvature
         if callback is not None:
             callback(it, st)
     return st, hist
+
+
+def mocca_nested(X, c, spec, lam: float, n_outer: int, n_inner: int, precond: str = "block",
+                 curvature: str = "clip", f0=None, rho=None, state: Optional[State] = None,
+                 callback: Optional[Callable[[int, int, State], None]] = None):
+    """MOCCA with nested loops (Sec. III names them as the remedy for the
+    divergence a single inner iteration can show): ``n_outer`` expansion
+    points, each the extrapolated iterate fbar at the start of its outer
+    iteration, and ``n_inner`` CPPD steps on the fixed convex quadratic
+    Q(K(f0) f) formed there (K, Sigma, T, r, D and u0 = K(f0) f0 all at f0).
+    n_inner = 1 is ``mocca``.  Starts from ``state`` if given, else from f0
+    (default 0) with y0 = 0; returns the final state.  callback(outer, inner,
+    state) after every step."""
+    L = X.shape[0]
+    P = X.shape[1]
+    if rho is None:
+        rho = np.asarray(X.sum(axis=1)).ravel()
+    st = state if state is not None else initial_state(spec.n_mat, P, L, spec.n_win, f0)
+    for o in range(n_outer):
+        expansion = st.fbar.copy()
+        for j in range(n_inner):
+            st = mocca_step(X, rho, st, c, spec, lam, precond, curvature, expansion=expansion)
+            if callback is not None:
+                callback(o, j, st)
+    return st

@@ -492,6 +492,65 @@ def test_planted_no_extrapolation_breaks_fejer(composition, curv):
     assert (np.diff(dist) > 1e-3 * dist[:-1]).any()
 
 
+def test_nested_one_inner_step_is_mocca(composition):
+    spec, X, rho, c, f0 = composition
+    for precond, curv in (("block", "clip"), ("diag", "window")):
+        a, _ = mocca.mocca(X, c, spec, 1e-5, 6, precond, curv, f0=f0, rho=rho)
+        b = mocca.mocca_nested(X, c, spec, 1e-5, 6, 1, precond, curv, f0=f0, rho=rho)
+        assert np.array_equal(a.f, b.f) and np.array_equal(a.fbar, b.fbar) and np.array_equal(a.y, b.y)
+
+
+@pytest.mark.parametrize("curv", ["window", "clip"])
+def test_nested_inner_loop_reaches_the_minimiser_at_its_expansion_point(composition, curv):
+    # one outer iteration from f = fbar = f0: the inner steps run CPPD on
+    # Q(K(f0) f) and end at its closed-form minimiser
+    spec, X, rho, c, f0 = composition
+    lam = 1e-5
+    _, fs, _, _ = _fixed_quadratic(spec, X, rho, c, f0, lam, "block", curv)
+    st = mocca.mocca_nested(X, c, spec, lam, 1, 2000, "block", curv, f0=f0, rho=rho)
+    assert np.linalg.norm(st.f.ravel() - fs) <= 1e-5 * np.linalg.norm(fs)
+
+
+def test_nested_outer_loop_re_expands_at_fbar(composition):
+    # after a short outer iteration fbar and f differ; the next outer
+    # iteration converges to the minimiser of the quadratic at fbar, not at f
+    spec, X, rho, c, f0 = composition
+    lam = 1e-5
+    s1 = mocca.mocca_nested(X, c, spec, lam, 1, 3, "block", "window", f0=f0, rho=rho)
+    _, fs_bar, _, _ = _fixed_quadratic(spec, X, rho, c, s1.fbar, lam, "block", "window")
+    _, fs_f, _, _ = _fixed_quadratic(spec, X, rho, c, s1.f, lam, "block", "window")
+    assert np.linalg.norm(fs_bar - fs_f) > 1e-3 * np.linalg.norm(fs_bar)
+    s2 = mocca.mocca_nested(X, c, spec, lam, 1, 2000, "block", "window", rho=rho, state=s1)
+    assert np.linalg.norm(s2.f.ravel() - fs_bar) <= 1e-5 * np.linalg.norm(fs_bar)
+    # and two outer iterations in one call equal two calls of one
+    both = mocca.mocca_nested(X, c, spec, lam, 2, 3, "block", "window", f0=f0, rho=rho)
+    again = mocca.mocca_nested(X, c, spec, lam, 1, 3, "block", "window", rho=rho, state=s1)
+    assert np.array_equal(both.f, again.f) and np.array_equal(both.y, again.y)
+
+
+def test_nested_loops_stabilise_a_step_where_one_inner_iteration_diverges(composition):
+    # Sec. III: MOCCA can diverge with a single inner iteration per expansion
+    # point; at lambda = 2e-6 it does here from f = 0, while five inner
+    # iterations per expansion point fit the data below the noise level
+    spec, X, rho, c, _ = composition
+    lam, steps = 2e-6, 200
+    f_true = synth.inserts_phantom(8, 20.0).reshape(3, -1)
+    floor = model.image_objective(X, f_true, c, spec)
+
+    def final_dtpl(n_inner):
+        with np.errstate(all="ignore"):
+            try:
+                st = mocca.mocca_nested(X, c, spec, lam, steps // n_inner, n_inner, "block", "clip", rho=rho)
+            except np.linalg.LinAlgError:  # T^-1 blocks no longer invertible
+                return np.inf
+            d = model.image_objective(X, st.f, c, spec)
+        return d if np.isfinite(d) else np.inf
+
+    start = model.image_objective(X, np.zeros_like(f_true), c, spec)
+    assert final_dtpl(1) > start
+    assert final_dtpl(5) < floor
+
+
 def _generic_mocca_step(spec, X, rho, c, state, lam, curv):
     """One MOCCA step from the definitions, dense: K(f0) = A(f0) Z at the
     expansion point f0 = fbar_n, Sigma and T^-1 from the paper's sums over
