@@ -219,6 +219,24 @@ int osscir_diag_spc_steps(osscir_plan plan, const float *G, double lambda, float
 int osscir_mocca_iterate(osscir_plan plan, const osscir_params *params, osscir_state *state, int32_t n_iter,
                          double *dtpl, osscir_stream stream);
 
+/* MOCCA with nested loops (Sec. III: with a single inner iteration per
+ * expansion point MOCCA can diverge; nested inner and outer loops are the
+ * remedy the paper sets aside for speed).
+ * n_outer expansion points, each f0 = fbar at the start of its outer
+ * iteration; n_inner CPPD steps on the fixed convex quadratic Q(K(f0) f),
+ * with K, Sigma, T, r, D_l and u0 = K(f0) f0 all formed at f0:
+ *   y_{j+1}    = prox_{Sigma Q*}(y_j + Sigma K(f0) fbar_j)
+ *              = y_j + Sigma (Sigma + D_l)^-1 (r_l + D_l K(f0) (fbar_j - f0) - y_j)
+ *   f_{j+1}    = f_j - T K(f0)^T y_{j+1},   fbar_{j+1} = 2 f_{j+1} - f_j.
+ * The first inner step of every outer iteration is the osscir_mocca_iterate
+ * step, so n_inner = 1 gives osscir_mocca_iterate's results bit for bit.
+ * p0: DEVICE [3][V][D] floats, caller-owned scratch; on return it holds
+ * X f0 of the last expansion point.  dtpl as in osscir_mocca_iterate, with
+ * n_outer * n_inner entries (one per inner step).  EINVAL if n_outer < 0,
+ * n_inner < 1, n_outer * n_inner overflows int32, or p0 is NULL. */
+int osscir_mocca_iterate_nested(osscir_plan plan, const osscir_params *params, osscir_state *state,
+                                int32_t n_outer, int32_t n_inner, float *p0, double *dtpl, osscir_stream stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): exactly
  * osscir_mocca_iterate (same kernels, same results bit for bit) on the state

@@ -519,6 +519,7 @@ struct IterArgs {
   void *pack;
   bool block, clip, fp64;
   float lam;
+  const float *pbar = nullptr;  // inner iterations of nested loops: fbar's line integrals (p: the expansion point's)
 };
 
 int check_iter(osscir_plan plan, const osscir_params *params, const osscir_state *state, IterArgs *out) {
@@ -559,7 +560,7 @@ int run_stage(const ScanDesc &sd, const IterArgs &a, osscir_state *state, int st
         OSSCIR_HIP(launch_forward(sd, state->fbar, 3, a.p, a.pack, st), "mocca: forward projection");
       break;
     case 1:
-      OSSCIR_HIP(launch_spectral_dual(sd, a.p, state->c, state->y, a.qS, a.lam, a.clip, a.block, a.fp64, st),
+      OSSCIR_HIP(launch_spectral_dual(sd, a.p, state->c, state->y, a.qS, a.lam, a.clip, a.block, a.fp64, st, a.pbar),
                  "mocca: spectral model and dual step");
       break;
     case 2:
@@ -590,6 +591,42 @@ int osscir_mocca_iterate(osscir_plan plan, const osscir_params *params, osscir_s
     const bool packed = chain && it > 0, pack_next = chain && it + 1 < n_iter;
     for (int stage = 0; stage < 3; ++stage)
       if ((rc = run_stage(sd, a, state, stage, st, packed, pack_next))) return rc;
+    if (dtpl)
+      OSSCIR_HIP(launch_dtpl(sd, state->f, state->c, a.p, a.pack, a.partial, dtpl + it, st), "mocca: D_TPL");
+  }
+  return OSSCIR_OK;
+}
+
+int osscir_mocca_iterate_nested(osscir_plan plan, const osscir_params *params, osscir_state *state, int32_t n_outer,
+                                int32_t n_inner, float *p0, double *dtpl, osscir_stream stream) {
+  IterArgs a;
+  int rc = check_iter(plan, params, state, &a);
+  if (rc) return rc;
+  if (n_outer < 0 || n_inner < 1) return fail(OSSCIR_EINVAL, "nested: need n_outer >= 0 and n_inner >= 1");
+  if (n_outer > INT32_MAX / n_inner) return fail(OSSCIR_EINVAL, "nested: n_outer * n_inner overflows");
+  if (!p0) return fail(OSSCIR_EINVAL, "nested: null p0");
+  const ScanDesc &sd = plan->sd;
+  hipStream_t st = (hipStream_t)stream;
+  const int total = n_outer * n_inner;
+  const bool chain = dtpl == nullptr;  // as in osscir_mocca_iterate
+  // the first inner iteration of an outer one is the plain MOCCA step at
+  // f0 = fbar, its forward projection kept in p0; the others project fbar
+  // into the workspace and take the model from p0
+  IterArgs first = a, inner = a;
+  first.p = p0;
+  inner.pbar = a.p;
+  inner.p = p0;
+  for (int it = 0; it < total; ++it) {
+    const bool packed = chain && it > 0, pack_next = chain && it + 1 < total;
+    const bool outer_start = it % n_inner == 0;
+    if (outer_start) {
+      if ((rc = run_stage(sd, first, state, 0, st, packed, pack_next))) return rc;
+      if ((rc = run_stage(sd, first, state, 1, st, packed, pack_next))) return rc;
+    } else {
+      if ((rc = run_stage(sd, a, state, 0, st, packed, pack_next))) return rc;
+      if ((rc = run_stage(sd, inner, state, 1, st, packed, pack_next))) return rc;
+    }
+    if ((rc = run_stage(sd, a, state, 2, st, packed, pack_next))) return rc;
     if (dtpl)
       OSSCIR_HIP(launch_dtpl(sd, state->f, state->c, a.p, a.pack, a.partial, dtpl + it, st), "mocca: D_TPL");
   }

@@ -9,9 +9,12 @@ namespace osscir {
 hipError_t launch_spectral_model(const ScanDesc &sd, const float *p, const float *c, float *chat, float *r,
                                  float *G, float *H, float *Hp, bool fp64, hipStream_t st);
 
-// y, qS updated from p (line integrals at the expansion point) and counts c.
+// y, qS updated from p (line integrals at the expansion point) and counts c;
+// pbar (optional): the line integrals of fbar when they differ from p (inner
+// iterations of nested loops).
 hipError_t launch_spectral_dual(const ScanDesc &sd, const float *p, const float *c, float *y, float *qS,
-                                float lambda, bool clip, bool block, bool fp64, hipStream_t st);
+                                float lambda, bool clip, bool block, bool fp64, hipStream_t st,
+                                const float *pbar = nullptr);
 
 // back-projection of qS fused with the primal step and the extrapolation;
 // pack (optional): packed images (launch_pack's layout, borders already

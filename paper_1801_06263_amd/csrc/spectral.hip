@@ -56,23 +56,26 @@ __global__ void __launch_bounds__(256) k_spectral_model(ScanDesc sd, const float
 
 // ---------------------------------------------------------------- dual step
 
-template <typename T, bool CLIP, bool BLOCK, bool PB>
+// NEST: pbar (the line integrals of fbar) is read, p is the expansion point's
+template <typename T, bool CLIP, bool BLOCK, bool PB, bool NEST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_spectral_dual(ScanDesc sd, const float *__restrict__ p,
                                                         const float *__restrict__ c, float *__restrict__ y,
-                                                        float *__restrict__ qS, float lambda) {
-  spectral_dual_ray<T, CLIP, BLOCK, PB>(sd, p, c, y, qS, lambda, blockIdx.x * blockDim.x + threadIdx.x);
+                                                        float *__restrict__ qS, float lambda,
+                                                        const float *__restrict__ pbar) {
+  spectral_dual_ray<T, CLIP, BLOCK, PB, false, NEST>(sd, p, c, y, qS, lambda, blockIdx.x * blockDim.x + threadIdx.x,
+                                                     nullptr, pbar);
 }
 
 // energy sums on the matrix cores (shared response table, 64-ray waves)
-template <typename T, bool CLIP, bool BLOCK>
+template <typename T, bool CLIP, bool BLOCK, bool NEST>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))
     k_spectral_dual_mfma(ScanDesc sd, const float *__restrict__ p, const float *__restrict__ c, float *__restrict__ y,
-                         float *__restrict__ qS, float lambda) {
+                         float *__restrict__ qS, float lambda, const float *__restrict__ pbar) {
   extern __shared__ float stab[];
   stage_table(sd, stab);
   __syncthreads();
-  spectral_dual_ray<T, CLIP, BLOCK, false, true>(sd, p, c, y, qS, lambda, blockIdx.x * blockDim.x + threadIdx.x,
-                                                 stab);
+  spectral_dual_ray<T, CLIP, BLOCK, false, true, NEST>(sd, p, c, y, qS, lambda,
+                                                       blockIdx.x * blockDim.x + threadIdx.x, stab, pbar);
 }
 
 // ---------------------------------------------------------------- steps only
@@ -223,22 +226,29 @@ hipError_t launch_spectral_model(const ScanDesc &sd, const float *p, const float
 }
 
 hipError_t launch_spectral_dual(const ScanDesc &sd, const float *p, const float *c, float *y, float *qS,
-                                float lambda, bool clip, bool block, bool fp64, hipStream_t st) {
+                                float lambda, bool clip, bool block, bool fp64, hipStream_t st, const float *pbar) {
   // matrix-core energy sums: a plan property (shared table within 64 KB of LDS)
   // 512-ray workgroups: the table is staged once per eight waves (3% faster than four)
   const size_t mfma_lds = mfma_lds_bytes(sd.n_energy, 8);
   const bool mfma = sd.mfma != 0;
-#define OSSCIR_DUAL(T, C, B)                                                                                \
+#define OSSCIR_DUAL_N(T, C, B, N)                                                                            \
   do {                                                                                                      \
     if (sd.per_bin)                                                                                         \
-      hipLaunchKernelGGL((k_spectral_dual<T, C, B, true>), ray_grid(sd), dim3(256), 0, st, sd, p, c, y, qS,  \
-                         lambda);                                                                           \
+      hipLaunchKernelGGL((k_spectral_dual<T, C, B, true, N>), ray_grid(sd), dim3(256), 0, st, sd, p, c, y,   \
+                         qS, lambda, pbar);                                                                 \
     else if (mfma)                                                                                          \
-      hipLaunchKernelGGL((k_spectral_dual_mfma<T, C, B>), dim3((sd.n_rays + 511) / 512), dim3(512), mfma_lds, st, sd, p, c, y, \
-                         qS, lambda);                                                                       \
+      hipLaunchKernelGGL((k_spectral_dual_mfma<T, C, B, N>), dim3((sd.n_rays + 511) / 512), dim3(512),       \
+                         mfma_lds, st, sd, p, c, y, qS, lambda, pbar);                                      \
     else                                                                                                    \
-      hipLaunchKernelGGL((k_spectral_dual<T, C, B, false>), ray_grid(sd), dim3(256), 0, st, sd, p, c, y, qS, \
-                         lambda);                                                                           \
+      hipLaunchKernelGGL((k_spectral_dual<T, C, B, false, N>), ray_grid(sd), dim3(256), 0, st, sd, p, c, y,  \
+                         qS, lambda, pbar);                                                                 \
+  } while (0)
+#define OSSCIR_DUAL(T, C, B)                      \
+  do {                                            \
+    if (pbar)                                     \
+      OSSCIR_DUAL_N(T, C, B, true);               \
+    else                                          \
+      OSSCIR_DUAL_N(T, C, B, false);              \
   } while (0)
   if (fp64) {
     if (clip) {
@@ -254,6 +264,7 @@ hipError_t launch_spectral_dual(const ScanDesc &sd, const float *p, const float 
     }
   }
 #undef OSSCIR_DUAL
+#undef OSSCIR_DUAL_N
   return hipGetLastError();
 }
 

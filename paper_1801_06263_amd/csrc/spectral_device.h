@@ -302,10 +302,16 @@ __device__ __forceinline__ void ray_hessian(const T a[kWin][kMat], const T cw[kW
 // (I + Sigma^-1/2 D Sigma^-1/2) z = Sigma^-1/2 (r - y).
 // MFMA: the energy sums on the matrix cores (energy_sums_mfma; stab = the
 // table staged in LDS); every thread of the workgroup must call it.
-template <typename T, bool CLIP, bool BLOCK, bool PB = false, bool MFMA = false>
+// NEST (inner iterations of nested loops): p holds the line integrals of the
+// expansion point f0, where the model (G, r, D) and the steps are formed,
+// and pbar those of fbar_n.  The dual step at v = y + Sigma G pbar with
+// u0 = G p is the step above with r replaced by r + D G (pbar - p); with
+// D = G^+T H^+ G^+ (G of full column rank) D G = G (G^T G)^-1 H^+.
+template <typename T, bool CLIP, bool BLOCK, bool PB = false, bool MFMA = false, bool NEST = false>
 __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const float *__restrict__ p,
                                                   const float *__restrict__ c, float *__restrict__ y,
-                                                  float *__restrict__ qS, float lambda, int l, float *stab = nullptr) {
+                                                  float *__restrict__ qS, float lambda, int l, float *stab = nullptr,
+                                                  const float *__restrict__ pbar = nullptr) {
   static_assert(!(MFMA && PB), "the MFMA sums need one shared response table");
   const int L = sd.n_rays;
   float g[kWin], af[kWin * kMat], hb[kWin * 6], n0[kWin];
@@ -369,8 +375,17 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
       for (int m = 0; m < 3; ++m) extra[m] += fabs(a[w][m]);
     }
   }
+  T dp[kMat];  // pbar - p (NEST)
+  if (NEST) {
+#pragma unroll
+    for (int m = 0; m < kMat; ++m) dp[m] = (T)pbar[m * L + l] - (T)p[m * L + l];
+  }
   // dual step
   if (!CLIP) {
+    if (NEST) {
+#pragma unroll
+      for (int w = 0; w < kWin; ++w) rw[w] += cw[w] * (a[w][0] * dp[0] + a[w][1] * dp[1] + a[w][2] * dp[2]);
+    }
 #pragma unroll
     for (int w = 0; w < kWin; ++w) yw[w] = (cw[w] * yw[w] + sig[w] * rw[w]) / (cw[w] + sig[w]);
   } else {
@@ -425,6 +440,19 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
     for (int w = 0; w < kWin; ++w)
 #pragma unroll
       for (int v = 0; v < kWin; ++v) Mm[w][v] = PH[w][0] * P[v][0] + PH[w][1] * P[v][1] + PH[w][2] * P[v][2];
+    if (NEST) {
+      // G (G^T G)^-1 = (P~ rows scaled back by Sigma^1/2, columns by C^-1)
+      T v[3];  // C^-1 H^+ dp
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        T hd = T(0);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) hd += hp[n <= m ? ut(n, m) : ut(m, n)] * dp[m];
+        v[n] = hd * ic[n];
+      }
+#pragma unroll
+      for (int w = 0; w < kWin; ++w) rw[w] += ss[w] * (P[w][0] * v[0] + P[w][1] * v[1] + P[w][2] * v[2]);
+    }
     T bt[kWin], z[kWin];
 #pragma unroll
     for (int w = 0; w < kWin; ++w) bt[w] = (rw[w] - yw[w]) * is[w];

@@ -74,6 +74,8 @@ SIGNATURES = {
                                         c_void_p]),
     "osscir_mocca_iterate": (c_int32, [c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_State), c_int32, c_void_p,
                                        c_void_p]),
+    "osscir_mocca_iterate_nested": (c_int32, [c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_State), c_int32,
+                                              c_int32, c_void_p, c_void_p, c_void_p]),
     "osscir_mocca_stage": (c_int32, [c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_State), c_int32, c_void_p]),
     "osscir_mocca_iterate_noalloc": (c_int32, [c_void_p, ctypes.POINTER(_Params), c_void_p, c_void_p, c_void_p,
                                                c_void_p, c_int32, c_void_p, c_void_p]),
@@ -301,6 +303,25 @@ class Plan:
         _check(_lib.osscir_mocca_iterate(self._h, ctypes.byref(prm), ctypes.byref(st), int(n_iter),
                                          _dev(out) if dtpl else None, _stream_handle(stream)))
         return out
+
+    def mocca_iterate_nested(self, state: State, params: Params, n_outer: int, n_inner: int, p0=None,
+                             dtpl: bool = False, stream=None):
+        """Nested loops in place: n_outer expansion points (f0 = fbar at each
+        outer start), n_inner CPPD steps on the quadratic at each.  p0: an
+        optional [3, V, D] float32 device tensor for X f0 (allocated if None;
+        returned).  Returns (p0, D_TPL [n_outer * n_inner] float64 or None)."""
+        import torch
+        V, D = self.sino_shape
+        if p0 is None:
+            p0 = torch.empty((3, V, D), dtype=torch.float32, device="cuda")
+        st = self._c_state(state)
+        total = max(int(n_outer) * int(n_inner), 1)
+        out = torch.empty(total, dtype=torch.float64, device="cuda") if dtpl else None
+        prm = params.to_c()
+        _check(_lib.osscir_mocca_iterate_nested(self._h, ctypes.byref(prm), ctypes.byref(st), int(n_outer),
+                                                int(n_inner), _dev(p0, (3, V, D), torch.float32, "p0"),
+                                                _dev(out) if dtpl else None, _stream_handle(stream)))
+        return p0, out
 
     def mocca_iterate_noalloc(self, state: State, params: Params, n_iter: int, dtpl=None, stream=None):
         """As mocca_iterate, with the library's static scratch in place of
