@@ -262,13 +262,19 @@ CONV_GRIDS = {
     "block": (5e-9, 1e-8, 2e-8, 5e-8, 1e-7, 2e-7, 3e-7, 5e-7),
     "mupc": (3e-7, 1e-6, 2e-6, 5e-6, 1e-5, 2e-5, 5e-5),
     "diag": (1e-9, 1e-8, 3e-8, 1e-7, 3e-7, 1e-6),
+    # block SPC with nested loops: k inner steps per expansion point, the
+    # same number of steps in all (each step costs one single-loop iteration)
+    "nested2": (2e-8, 5e-8, 1e-7, 2e-7, 5e-7, 1e-6, 2e-6, 5e-6),
+    "nested4": (2e-8, 5e-8, 1e-7, 2e-7, 5e-7, 1e-6, 2e-6, 5e-6, 1e-5),
+    "nested8": (5e-8, 1e-7, 2e-7, 5e-7, 1e-6, 2e-6, 5e-6, 1e-5, 2e-5),
 }
 
 
 def convergence_leg(spec_str: str):
     """D_TPL(c, chat(f_n)) per iteration (the paper's Fig. 3 quantity) for
     block-diagonal SPC, mu-PC (diagonal SPC in the orthonormal material
-    basis) and diagonal SPC, each over a lambda grid, clipped curvature; the
+    basis), diagonal SPC and block SPC with nested loops (2, 4 or 8 inner
+    steps per expansion point), each over a lambda grid, clipped curvature; the
     best lambda per method is the one with the lowest final D_TPL."""
     import numpy as np
     import torch
@@ -296,8 +302,14 @@ def convergence_leg(spec_str: str):
             for lam in lams:
                 pl = plan_t if method == "mupc" else plan
                 st = pl.new_state(c)
-                prm = Params(lam, "diag" if method == "mupc" else method, "clip", True)
-                d = pl.mocca_iterate(st, prm, n_iter, dtpl=True).double().cpu().numpy()
+                if method.startswith("nested"):
+                    k = int(method[len("nested"):])
+                    _, d = pl.mocca_iterate_nested(st, Params(lam, "block", "clip", True), n_iter // k, k,
+                                                   dtpl=True)
+                    d = d.double().cpu().numpy()
+                else:
+                    prm = Params(lam, "diag" if method == "mupc" else method, "clip", True)
+                    d = pl.mocca_iterate(st, prm, n_iter, dtpl=True).double().cpu().numpy()
                 fin = float(d[-1]) if np.isfinite(d[-1]) else float("inf")
                 finals.append(fin)
                 curves[lam] = {m: (float(d[m - 1]) if np.isfinite(d[m - 1]) else None) for m in marks}
