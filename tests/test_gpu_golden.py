@@ -81,3 +81,57 @@ def test_large_trajectory_fp32_tail(large):
     rels, d, ref = check_trajectory(large, False)
     assert max(rels) <= 3e-3
     np.testing.assert_allclose(d, ref, rtol=3e-3)
+
+
+# ---------------------------------------------------------------- the paper's comparisons (Sec. III, Fig. 3)
+#
+# D_TPL(c, chat(f_n)) from f = 0 for each method at the best lambda of a grid
+# (lowest final value), clipped curvature, FP64 tail; on the inputs above
+# (oracle Poisson counts).  Only runs that converge are made.
+
+def dtpl_curve(plan, c, prm, n_iter, nested=0):
+    st = plan.new_state(c)
+    if nested:
+        _, d = plan.mocca_iterate_nested(st, prm, n_iter // nested, nested, dtpl=True)
+    else:
+        d = plan.mocca_iterate(st, prm, n_iter, dtpl=True)
+    d = host(d)
+    assert np.isfinite(d).all()
+    return d
+
+
+def test_claim_block_spc_beats_diagonal_spc_at_256(medium):
+    """Block SPC at its best lambda ends 500 iterations far below diagonal
+    SPC at its best lambda (stored run: 2.0e5 against 2.8e8)."""
+    from paper_1801_06263_amd import Params
+    pr, c, _, plan, _ = medium
+    block = min(dtpl_curve(plan, c, Params(lam, "block", "clip", True), 500)[-1] for lam in (2e-7, 3e-7, 5e-7))
+    diag = min(dtpl_curve(plan, c, Params(lam, "diag", "clip", True), 500)[-1] for lam in (3e-8, 1e-7, 3e-7))
+    print(f"256^2 after 500: block {block:.3e}, diagonal {diag:.3e}")
+    assert block < 1e-2 * diag
+
+
+def test_claim_block_spc_leads_mu_pc_early_at_256(medium):
+    """After 100 iterations block SPC is ahead of mu-PC (diagonal SPC in the
+    orthonormal material basis), each at its best lambda."""
+    from paper_1801_06263_amd import Params, Plan
+    from paper_1801_06263_amd.osscir import mu_pc_spectral
+    pr, c, _, plan, _ = medium
+    spec_t, _ = mu_pc_spectral(pr.spec)
+    plan_t = Plan(pr.geom, spec_t)
+    block = min(dtpl_curve(plan, c, Params(lam, "block", "clip", True), 100)[-1] for lam in (3e-7, 5e-7))
+    mupc = min(dtpl_curve(plan_t, c, Params(lam, "diag", "clip", True), 100)[-1] for lam in (5e-6, 1e-5, 2e-5))
+    print(f"256^2 after 100: block {block:.3e}, mu-PC {mupc:.3e}")
+    assert block < 0.5 * mupc
+
+
+def test_nested_loops_take_longer_steps_at_512(large):
+    """Four inner steps per expansion point at lambda = 1e-7 (5x the single
+    loop's largest stable lambda on this scan) end 300 steps well below the
+    single loop at 2e-8 (1000-step runs: 5.1e6 against 3.2e7)."""
+    from paper_1801_06263_amd import Params
+    pr, c, _, plan, _ = large
+    single = dtpl_curve(plan, c, Params(2e-8, "block", "clip", True), 300)
+    nested = dtpl_curve(plan, c, Params(1e-7, "block", "clip", True), 300, nested=4)
+    print(f"512^2 after 300: single {single[-1]:.3e}, nested {nested[-1]:.3e}")
+    assert nested[-1] < 0.5 * single[-1]
