@@ -267,14 +267,16 @@ CONV_GRIDS = {
     "nested2": (2e-8, 5e-8, 1e-7, 2e-7, 5e-7, 1e-6, 2e-6, 5e-6),
     "nested4": (2e-8, 5e-8, 1e-7, 2e-7, 5e-7, 1e-6, 2e-6, 5e-6, 1e-5),
     "nested8": (5e-8, 1e-7, 2e-7, 5e-7, 1e-6, 2e-6, 5e-6, 1e-5, 2e-5),
+    # mu-PC with the same nesting, for a like-for-like comparison
+    "mupc_nested4": (1e-6, 2e-6, 5e-6, 1e-5, 2e-5, 5e-5, 1e-4, 2e-4),
 }
 
 
 def convergence_leg(spec_str: str):
     """D_TPL(c, chat(f_n)) per iteration (the paper's Fig. 3 quantity) for
     block-diagonal SPC, mu-PC (diagonal SPC in the orthonormal material
-    basis), diagonal SPC and block SPC with nested loops (2, 4 or 8 inner
-    steps per expansion point), each over a lambda grid, clipped curvature; the
+    basis), diagonal SPC, block SPC with nested loops (2, 4 or 8 inner
+    steps per expansion point) and mu-PC with 4, each over a lambda grid, clipped curvature; the
     best lambda per method is the one with the lowest final D_TPL."""
     import numpy as np
     import torch
@@ -300,12 +302,12 @@ def convergence_leg(spec_str: str):
         for method, lams in CONV_GRIDS.items():
             finals, curves = [], {}
             for lam in lams:
-                pl = plan_t if method == "mupc" else plan
+                pl = plan_t if method.startswith("mupc") else plan
                 st = pl.new_state(c)
-                if method.startswith("nested"):
-                    k = int(method[len("nested"):])
-                    _, d = pl.mocca_iterate_nested(st, Params(lam, "block", "clip", True), n_iter // k, k,
-                                                   dtpl=True)
+                if "nested" in method:
+                    k = int(method.split("nested")[1])
+                    pre = "diag" if method.startswith("mupc") else "block"
+                    _, d = pl.mocca_iterate_nested(st, Params(lam, pre, "clip", True), n_iter // k, k, dtpl=True)
                     d = d.double().cpu().numpy()
                 else:
                     prm = Params(lam, "diag" if method == "mupc" else method, "clip", True)
