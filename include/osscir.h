@@ -343,6 +343,18 @@ int osscir_batch_destroy(osscir_batch batch);
  * plan must outlive the binding. */
 int osscir_batch_set_slot(osscir_batch batch, int32_t slot, osscir_plan plan, const osscir_state *state,
                           double lambda, int32_t max_iter, double tol, osscir_stream stream);
+/* osscir_batch_set_slot for MOCCA with nested loops (as
+ * osscir_mocca_iterate_nested): n_inner steps per expansion point, the
+ * expansion point re-taken at fbar every n_inner steps counted from binding;
+ * iters, max_iter and the relative change count inner steps.  p0: DEVICE
+ * [3][V][D] floats of caller memory that the slot uses while bound
+ * (X f0 of its current expansion point); ignored when n_inner = 1, which is
+ * osscir_batch_set_slot.  A slot computes bit for bit what
+ * osscir_mocca_iterate_nested computes for its scan.  EINVAL if n_inner < 1
+ * or (n_inner > 1 and p0 is NULL). */
+int osscir_batch_set_slot_nested(osscir_batch batch, int32_t slot, osscir_plan plan, const osscir_state *state,
+                                 double lambda, int32_t max_iter, double tol, int32_t n_inner, float *p0,
+                                 osscir_stream stream);
 /* Unbind a slot (state becomes OSSCIR_SLOT_EMPTY). */
 int osscir_batch_clear_slot(osscir_batch batch, int32_t slot);
 

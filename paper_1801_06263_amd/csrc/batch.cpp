@@ -27,6 +27,8 @@ struct HostSlot {
   osscir_plan plan = nullptr;
   osscir_state state{};
   float lambda = 0.0f;
+  int n_inner = 1;       // inner steps per expansion point
+  float *p0 = nullptr;   // [3][L] caller memory when n_inner > 1
 };
 
 struct ListBuf {
@@ -91,6 +93,7 @@ struct osscir_batch_s {
   int partial_cap = 0;
   ListBuf lists[kLists];
   bool any_wide = false;
+  bool any_nested = false;      // some bound slot runs nested loops
   size_t spec_lds = 0;          // dynamic LDS of the spectral launch
   hipEvent_t staged = nullptr;  // the last upload from the staging buffers
   bool staged_pending = false;
@@ -98,7 +101,7 @@ struct osscir_batch_s {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  bool graph_ok = false, graph_wide = false;
+  bool graph_ok = false, graph_wide = false, graph_nested = false;
   size_t graph_spec_lds = 0;
 };
 
@@ -153,6 +156,8 @@ SlotDesc make_desc(const HostSlot &hs) {
   d.pk_yx = d.pk_xy + np * np;
   d.lambda = hs.lambda;
   d.n_tiles = tiles_of(sd);
+  d.n_inner = hs.n_inner;
+  d.p0 = hs.p0;
   return d;
 }
 
@@ -184,7 +189,7 @@ int flush(osscir_batch b, hipStream_t st) {
   const osscir_batch_config &c = b->cfg;
   // slot table and tile offsets (slot order)
   int tiles = 0;
-  bool any_wide = false;
+  bool any_wide = false, any_nested = false;
   size_t spec_lds = 0;
   std::vector<int> order;
   for (int s = 0; s < b->max_slots; ++s) {
@@ -197,6 +202,7 @@ int flush(osscir_batch b, hipStream_t st) {
     b->h_slots[s].first_tile = tiles;
     tiles += b->h_slots[s].n_tiles;
     any_wide |= hs.plan->sd.bp_wide != 0;
+    any_nested |= hs.n_inner > 1;
     if (hs.plan->sd.mfma) spec_lds = std::max(spec_lds, mfma_lds_bytes(hs.plan->sd.n_energy, c.spec_rays / 64));
     order.push_back(s);
   }
@@ -276,6 +282,7 @@ int flush(osscir_batch b, hipStream_t st) {
   OSSCIR_HIP(hipEventRecord(b->staged, st), "batch: recording the upload");
   b->staged_pending = true;
   b->any_wide = any_wide;
+  b->any_nested = any_nested;
   b->spec_lds = spec_lds;
   b->dirty = false;
   return OSSCIR_OK;
@@ -294,8 +301,7 @@ int launch_iteration(osscir_batch b, hipStream_t st, hipEvent_t *ev = nullptr) {
              "batch: forward projection");
   if (ev) OSSCIR_HIP(hipEventRecord(ev[1], st), "batch: event");
   OSSCIR_HIP(launch_batch_spectral_dual(b->d_slots, b->d_status, worklist(b, kListSpec, c.spec_wgs), c.spec_rays,
-                                        b->spec_lds,
-                                        b->clip, b->block, b->fp64, st),
+                                        b->spec_lds, b->clip, b->block, b->fp64, b->any_nested, st),
              "batch: spectral model and dual step");
   if (ev) OSSCIR_HIP(hipEventRecord(ev[2], st), "batch: event");
   OSSCIR_HIP(launch_batch_back_primal(b->d_slots, b->d_status, worklist(b, kListBp, c.bp_wgs), b->block, false,
@@ -333,6 +339,7 @@ int capture(osscir_batch b, hipStream_t st) {
   OSSCIR_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "batch: instantiating the graph");
   b->graph_ok = true;
   b->graph_wide = b->any_wide;
+  b->graph_nested = b->any_nested;
   b->graph_spec_lds = b->spec_lds;
   return OSSCIR_OK;
 }
@@ -395,8 +402,9 @@ int osscir_batch_destroy(osscir_batch batch) {
   return OSSCIR_OK;
 }
 
-int osscir_batch_set_slot(osscir_batch b, int32_t slot, osscir_plan plan, const osscir_state *state, double lambda,
-                          int32_t max_iter, double tol, osscir_stream stream) {
+int osscir_batch_set_slot_nested(osscir_batch b, int32_t slot, osscir_plan plan, const osscir_state *state,
+                                 double lambda, int32_t max_iter, double tol, int32_t n_inner, float *p0,
+                                 osscir_stream stream) {
   int rc = check_batch(b);
   if (rc) return rc;
   if (slot < 0 || slot >= b->max_slots) return fail(OSSCIR_EINVAL, "slot %d outside [0, %d)", slot, b->max_slots);
@@ -405,6 +413,8 @@ int osscir_batch_set_slot(osscir_batch b, int32_t slot, osscir_plan plan, const 
     return fail(OSSCIR_EINVAL, "batch: null state buffer");
   if (!(lambda > 0) || !std::isfinite(lambda)) return fail(OSSCIR_EINVAL, "lambda must be > 0");
   if (max_iter < 0 || !(tol >= 0) || !std::isfinite(tol)) return fail(OSSCIR_EINVAL, "need max_iter >= 0, tol >= 0");
+  if (n_inner < 1) return fail(OSSCIR_EINVAL, "nested: need n_inner >= 1 (got %d)", n_inner);
+  if (n_inner > 1 && !p0) return fail(OSSCIR_EINVAL, "nested: null p0");
   const WorkLayout wl = work_layout(plan->sd);
   if (state->work_bytes < wl.total)
     return fail(OSSCIR_ESTATE, "workspace %zu < %zu bytes", state->work_bytes, wl.total);
@@ -413,6 +423,8 @@ int osscir_batch_set_slot(osscir_batch b, int32_t slot, osscir_plan plan, const 
   hs.plan = plan;
   hs.state = *state;
   hs.lambda = (float)lambda;
+  hs.n_inner = n_inner;
+  hs.p0 = n_inner > 1 ? p0 : nullptr;
   SlotStatus st{};
   st.state = kSlotRunning;
   st.max_iter = max_iter;
@@ -424,6 +436,11 @@ int osscir_batch_set_slot(osscir_batch b, int32_t slot, osscir_plan plan, const 
   OSSCIR_HIP(launch_pack(plan->sd, state->fbar, 3, (char *)state->work + wl.pack, (hipStream_t)stream),
              "batch: packing fbar");
   return OSSCIR_OK;
+}
+
+int osscir_batch_set_slot(osscir_batch b, int32_t slot, osscir_plan plan, const osscir_state *state, double lambda,
+                          int32_t max_iter, double tol, osscir_stream stream) {
+  return osscir_batch_set_slot_nested(b, slot, plan, state, lambda, max_iter, tol, 1, nullptr, stream);
 }
 
 int osscir_batch_clear_slot(osscir_batch b, int32_t slot) {
@@ -445,7 +462,8 @@ int osscir_batch_iterate(osscir_batch b, int32_t n_iter, int32_t use_graph, ossc
   if ((rc = flush(b, st))) return rc;
   if (n_iter == 0) return OSSCIR_OK;
   if (use_graph) {
-    if (!b->graph_ok || b->graph_wide != b->any_wide || b->graph_spec_lds != b->spec_lds)
+    if (!b->graph_ok || b->graph_wide != b->any_wide || b->graph_nested != b->any_nested ||
+        b->graph_spec_lds != b->spec_lds)
       if ((rc = capture(b, st))) return rc;
     for (int i = 0; i < n_iter; ++i) OSSCIR_HIP(hipGraphLaunch(b->exec, st), "batch: graph launch");
   } else {
@@ -503,11 +521,12 @@ int osscir_batch_tune(osscir_batch b, int32_t iters_per_trial, osscir_batch_conf
     if (cfg_out) *cfg_out = b->cfg;
     return OSSCIR_OK;
   }
-  // snapshot of f, fbar, y and the status table
+  // snapshot of f, fbar, y (and p0 of nested slots) and the status table
   std::vector<size_t> off(bound.size() + 1, 0);
   for (size_t i = 0; i < bound.size(); ++i) {
-    const ScanDesc &sd = b->slots[bound[i]].plan->sd;
-    off[i + 1] = off[i] + 6 * (size_t)sd.n * sd.n + 4 * (size_t)sd.n_rays;
+    const HostSlot &hs = b->slots[bound[i]];
+    const ScanDesc &sd = hs.plan->sd;
+    off[i + 1] = off[i] + 6 * (size_t)sd.n * sd.n + (hs.n_inner > 1 ? 7 : 4) * (size_t)sd.n_rays;
   }
   float *snap = nullptr;
   OSSCIR_HIP(hipMalloc(&snap, off.back() * sizeof(float)), "tune: snapshot allocation");
@@ -526,10 +545,10 @@ int osscir_batch_tune(osscir_batch b, int32_t iters_per_trial, osscir_batch_conf
       const ScanDesc &sd = hs.plan->sd;
       const size_t nn3 = 3 * (size_t)sd.n * sd.n, y4 = 4 * (size_t)sd.n_rays;
       float *base = snap + off[i];
-      float *bufs[3] = {hs.state.f, hs.state.fbar, hs.state.y};
-      const size_t offs[3] = {0, nn3, 2 * nn3};
-      const size_t counts[3] = {nn3, nn3, y4};
-      for (int k = 0; k < 3; ++k) {
+      float *bufs[4] = {hs.state.f, hs.state.fbar, hs.state.y, hs.p0};
+      const size_t offs[4] = {0, nn3, 2 * nn3, 2 * nn3 + y4};
+      const size_t counts[4] = {nn3, nn3, y4, 3 * (size_t)sd.n_rays};
+      for (int k = 0; k < (hs.n_inner > 1 ? 4 : 3); ++k) {
         void *dst = save ? (void *)(base + offs[k]) : (void *)bufs[k];
         const void *src = save ? (const void *)bufs[k] : (const void *)(base + offs[k]);
         OSSCIR_HIP(hipMemcpyAsync(dst, src, counts[k] * sizeof(float), hipMemcpyDeviceToDevice, st), "tune: state copy");

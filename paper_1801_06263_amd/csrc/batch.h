@@ -34,10 +34,11 @@ struct SlotDesc {
   const float *c;
   float *p, *qS;          // [3][L], [L][12]
   float4 *pk_xy, *pk_yx;  // packed fbar (zero border of kPad)
+  float *p0;              // nested loops: X f0 of the current expansion point [3][L] (caller memory)
   float lambda;
   int first_tile;         // the slot's first entry in the per-tile partial sums
   int n_tiles;            // 16 x 16 tiles of the image
-  int pad;
+  int n_inner;            // inner steps per expansion point (1: single loop); step iters % n_inner of the outer one
 };
 
 // Device-owned progress of a slot.  The end-of-iteration kernel advances
@@ -66,8 +67,10 @@ hipError_t launch_batch_forward(const SlotDesc *slots, const SlotStatus *status,
                                 hipStream_t st);
 // lds: dynamic LDS bytes, enough for every bound slot with matrix-core energy
 // sums (mfma_lds_bytes at rays_per_wg / 64 waves), else 0
+// nested: some bound slot has n_inner > 1 (the kernel variant that handles them)
 hipError_t launch_batch_spectral_dual(const SlotDesc *slots, const SlotStatus *status, WorkList wl,
-                                      int rays_per_wg, size_t lds, bool clip, bool block, bool fp64, hipStream_t st);
+                                      int rays_per_wg, size_t lds, bool clip, bool block, bool fp64, bool nested,
+                                      hipStream_t st);
 hipError_t launch_batch_back_primal(const SlotDesc *slots, const SlotStatus *status, WorkList wl, bool block,
                                     bool wide, double2 *partial, hipStream_t st);
 hipError_t launch_batch_tick(const SlotDesc *slots, SlotStatus *status, const double2 *partial, int n_slots,

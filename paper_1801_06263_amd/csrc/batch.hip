@@ -43,7 +43,15 @@ __device__ __forceinline__ SlotDesc load_slot(const SlotDesc *slots, int s) {
   d.qS = as_global(q->qS);
   d.pk_xy = as_global(q->pk_xy);
   d.pk_yx = as_global(q->pk_yx);
+  d.p0 = as_global(q->p0);
   return d;
+}
+
+// Nested loops: the slot's step within its outer iteration (0 for a single
+// loop).  The first step projects into p0 and forms the model there; the
+// others project into p and keep the model at p0.
+__device__ __forceinline__ int slot_inner_step(const SlotStatus *status, int s, const SlotDesc &sl) {
+  return sl.n_inner > 1 ? as_const(status)[s].iters % sl.n_inner : 0;
 }
 
 __device__ __forceinline__ bool slot_running(const SlotStatus *status, int s) {
@@ -65,11 +73,15 @@ __global__ void __launch_bounds__(256, 6) kb_forward(const SlotDesc *__restrict_
     const SlotDesc sl = load_slot(slots, s);
     const int nchunk = (sl.sd.n_bins + R - 1) / R;
     const int v = local / nchunk;
-    forward_rays<false>(sl.sd, sl.pk_xy, sl.pk_yx, sl.p, sl.sd.n_rays, 3, v, (local - v * nchunk) * R, wb);
+    float *out = sl.n_inner > 1 && slot_inner_step(status, s, sl) == 0 ? sl.p0 : sl.p;
+    forward_rays<false>(sl.sd, sl.pk_xy, sl.pk_yx, out, sl.sd.n_rays, 3, v, (local - v * nchunk) * R, wb);
   }
 }
 
-template <typename T, bool CLIP, bool BLOCK>
+// NESTED: the variant launched while some slot runs nested loops (its
+// inner steps take the model from p0 and the dual step at p); the other
+// variant serves batches of single-loop slots only.
+template <typename T, bool CLIP, bool BLOCK, bool NESTED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) kb_spectral_dual(const SlotDesc *__restrict__ slots,
                                                          const SlotStatus *__restrict__ status, WorkList wl) {
   extern __shared__ float stab[];  // matrix-core sums: the slot's table, then transposition tiles
@@ -82,7 +94,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
     if (!slot_running(status, s)) continue;
     const SlotDesc sl = load_slot(slots, s);
     const int l = local * (int)blockDim.x + (int)threadIdx.x;
-    if (sl.sd.per_bin) {
+    if (NESTED) {
+      // one call per energy-sum mode: a nested slot's inner steps pass pbar
+      // (model at p0), its first step and single-loop slots pass none
+      const bool nest = sl.n_inner > 1;
+      const float *pm = nest ? sl.p0 : sl.p;
+      const float *pb = nest && slot_inner_step(status, s, sl) != 0 ? sl.p : nullptr;
+      if (sl.sd.per_bin) {
+        spectral_dual_ray<T, CLIP, BLOCK, true, false, true>(sl.sd, pm, sl.c, sl.y, sl.qS, sl.lambda, l, nullptr, pb);
+      } else if (sl.sd.mfma) {
+        __syncthreads();
+        stage_table(sl.sd, stab);
+        __syncthreads();
+        spectral_dual_ray<T, CLIP, BLOCK, false, true, true>(sl.sd, pm, sl.c, sl.y, sl.qS, sl.lambda, l, stab, pb);
+      } else {
+        spectral_dual_ray<T, CLIP, BLOCK, false, false, true>(sl.sd, pm, sl.c, sl.y, sl.qS, sl.lambda, l, nullptr,
+                                                              pb);
+      }
+    } else if (sl.sd.per_bin) {
       spectral_dual_ray<T, CLIP, BLOCK, true>(sl.sd, sl.p, sl.c, sl.y, sl.qS, sl.lambda, l);
     } else if (sl.sd.mfma) {  // uniform over the workgroup, as in the single-scan kernel
       __syncthreads();        // the previous item is done with the staged table and tiles
@@ -154,9 +183,16 @@ hipError_t launch_batch_forward(const SlotDesc *slots, const SlotStatus *status,
 }
 
 hipError_t launch_batch_spectral_dual(const SlotDesc *slots, const SlotStatus *status, WorkList wl,
-                                      int rays_per_wg, size_t lds, bool clip, bool block, bool fp64, hipStream_t st) {
+                                      int rays_per_wg, size_t lds, bool clip, bool block, bool fp64, bool nested,
+                                      hipStream_t st) {
   const dim3 g((unsigned)wl.wgs), b((unsigned)rays_per_wg);
-#define OSSCIR_BDUAL(T, C, B) hipLaunchKernelGGL((kb_spectral_dual<T, C, B>), g, b, lds, st, slots, status, wl)
+#define OSSCIR_BDUAL(T, C, B)                                                                                  \
+  do {                                                                                                        \
+    if (nested)                                                                                               \
+      hipLaunchKernelGGL((kb_spectral_dual<T, C, B, true>), g, b, lds, st, slots, status, wl);                \
+    else                                                                                                      \
+      hipLaunchKernelGGL((kb_spectral_dual<T, C, B, false>), g, b, lds, st, slots, status, wl);               \
+  } while (0)
   if (fp64) {
     if (clip) {
       if (block) OSSCIR_BDUAL(double, true, true); else OSSCIR_BDUAL(double, true, false);

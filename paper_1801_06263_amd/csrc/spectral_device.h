@@ -304,7 +304,8 @@ __device__ __forceinline__ void ray_hessian(const T a[kWin][kMat], const T cw[kW
 // table staged in LDS); every thread of the workgroup must call it.
 // NEST (inner iterations of nested loops): p holds the line integrals of the
 // expansion point f0, where the model (G, r, D) and the steps are formed,
-// and pbar those of fbar_n.  The dual step at v = y + Sigma G pbar with
+// and pbar those of fbar_n (pbar NULL: the step at the expansion point, the
+// same arithmetic as NEST = false).  The dual step at v = y + Sigma G pbar with
 // u0 = G p is the step above with r replaced by r + D G (pbar - p); with
 // D = G^+T H^+ G^+ (G of full column rank) D G = G (G^T G)^-1 H^+.
 template <typename T, bool CLIP, bool BLOCK, bool PB = false, bool MFMA = false, bool NEST = false>
@@ -376,13 +377,14 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
     }
   }
   T dp[kMat];  // pbar - p (NEST)
-  if (NEST) {
+  const bool shift = NEST && pbar != nullptr;  // uniform
+  if (shift) {
 #pragma unroll
     for (int m = 0; m < kMat; ++m) dp[m] = (T)pbar[m * L + l] - (T)p[m * L + l];
   }
   // dual step
   if (!CLIP) {
-    if (NEST) {
+    if (shift) {
 #pragma unroll
       for (int w = 0; w < kWin; ++w) rw[w] += cw[w] * (a[w][0] * dp[0] + a[w][1] * dp[1] + a[w][2] * dp[2]);
     }
@@ -440,7 +442,7 @@ __device__ __forceinline__ void spectral_dual_ray(const ScanDesc &sd, const floa
     for (int w = 0; w < kWin; ++w)
 #pragma unroll
       for (int v = 0; v < kWin; ++v) Mm[w][v] = PH[w][0] * P[v][0] + PH[w][1] * P[v][1] + PH[w][2] * P[v][2];
-    if (NEST) {
+    if (shift) {
       // G (G^T G)^-1 = (P~ rows scaled back by Sigma^1/2, columns by C^-1)
       T v[3];  // C^-1 H^+ dp
 #pragma unroll

@@ -85,6 +85,8 @@ SIGNATURES = {
     "osscir_material_transform": (c_int32, [_dp, c_void_p, c_void_p, c_int32, c_void_p]),
     "osscir_batch_create": (c_int32, [ctypes.POINTER(_Params), c_int32, ctypes.POINTER(c_void_p)]),
     "osscir_batch_destroy": (c_int32, [c_void_p]),
+    "osscir_batch_set_slot_nested": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.POINTER(_State), c_double,
+                                               c_int32, c_double, c_int32, c_void_p, c_void_p]),
     "osscir_batch_set_slot": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.POINTER(_State), c_double, c_int32,
                                         c_double, c_void_p]),
     "osscir_batch_clear_slot": (c_int32, [c_void_p, c_int32]),
@@ -452,11 +454,23 @@ class Batch:
             pass
 
     def set_slot(self, slot: int, plan: Plan, state: State, lam: float, max_iter: int = 0, tol: float = 0.0,
-                 stream=None):
+                 stream=None, n_inner: int = 1, p0=None):
+        """Bind a scan to a slot.  n_inner > 1: nested loops (as
+        Plan.mocca_iterate_nested), with p0 an optional [3, V, D] float32
+        device tensor the slot keeps X f0 in (allocated if None)."""
+        import torch
         st = plan._c_state(state)
-        _check(_lib.osscir_batch_set_slot(self._h, int(slot), plan._h, ctypes.byref(st), float(lam), int(max_iter),
-                                          float(tol), _stream_handle(stream)))
-        self._bound[int(slot)] = (plan, state)
+        if n_inner > 1:
+            V, D = plan.sino_shape
+            if p0 is None:
+                p0 = torch.empty((3, V, D), dtype=torch.float32, device="cuda")
+            p0_ptr = _dev(p0, (3, V, D), torch.float32, "p0")
+        else:
+            p0, p0_ptr = None, None
+        _check(_lib.osscir_batch_set_slot_nested(self._h, int(slot), plan._h, ctypes.byref(st), float(lam),
+                                                 int(max_iter), float(tol), int(n_inner), p0_ptr,
+                                                 _stream_handle(stream)))
+        self._bound[int(slot)] = (plan, state, p0)
 
     def clear_slot(self, slot: int):
         _check(_lib.osscir_batch_clear_slot(self._h, int(slot)))

@@ -37,6 +37,7 @@ class Request:
     max_iter: int = 0       # > 0: stop after this many iterations
     tol: float = 0.0        # > 0: stop once ||f_{n+1} - f_n|| / ||f_{n+1}|| <= tol
     arrival: float = 0.0    # seconds after the start of the run
+    n_inner: int = 1        # > 1: nested loops, n_inner steps per expansion point (iterations count steps)
 
 
 @dataclasses.dataclass
@@ -71,11 +72,12 @@ def plan_bytes(geom) -> int:
     return 36 * L + 32 * geom.n_views + 32 * np_ * np_ + 16 * nt * nt * geom.n_views + 512 * 48 * 4
 
 
-def request_bytes(geom, workspace_bytes: int) -> int:
+def request_bytes(geom, workspace_bytes: int, n_inner: int = 1) -> int:
     """Device bytes of one admitted request: f, fbar [3][n][n], y, c [4][L]
-    (FP32) and the iteration workspace."""
+    (FP32), the iteration workspace, and with nested loops the expansion
+    point's line integrals [3][L]."""
     L = geom.n_views * geom.n_bins
-    return 4 * (6 * geom.n * geom.n + 8 * L) + int(workspace_bytes)
+    return 4 * (6 * geom.n * geom.n + 8 * L + (3 * L if n_inner > 1 else 0)) + int(workspace_bytes)
 
 
 class Server:
@@ -133,8 +135,8 @@ class Server:
         plan if no admitted request has used that scan yet."""
         plan = self.plans.get((req.geom, spectral_key(req.spec)))
         if plan is not None:
-            return request_bytes(req.geom, plan.workspace_bytes)
-        return plan_bytes(req.geom) + request_bytes(req.geom, self._estimate_workspace(req.geom))
+            return request_bytes(req.geom, plan.workspace_bytes, req.n_inner)
+        return plan_bytes(req.geom) + request_bytes(req.geom, self._estimate_workspace(req.geom), req.n_inner)
 
     @staticmethod
     def _estimate_workspace(geom) -> int:
@@ -154,12 +156,13 @@ class Server:
         plan = self._plan(req)
         if plan is None:
             return False
-        cost = request_bytes(req.geom, plan.workspace_bytes)
+        cost = request_bytes(req.geom, plan.workspace_bytes, req.n_inner)
         if self.used + cost > self.hbm_budget:
             return False
         state = plan.new_state(req.counts)
         slot = self.free_slots.pop()
-        self.batch.set_slot(slot, plan, state, req.lam, max_iter=req.max_iter, tol=req.tol)
+        nested = {"n_inner": req.n_inner} if req.n_inner > 1 else {}
+        self.batch.set_slot(slot, plan, state, req.lam, max_iter=req.max_iter, tol=req.tol, **nested)
         self._charge(cost)
         self.active[slot] = (req, state, now, cost)
         return True

@@ -327,3 +327,94 @@ def test_batch_argument_errors(scans):
         b.clear_slot(-1)
     b.iterate(3)  # nothing bound: a no-op
     assert all(s[0] == 0 for s in b.status())
+
+
+# ---------------------------------------------------------------- nested loops in a batch
+
+def nested_run(plan, c, params, chunks):
+    """osscir_mocca_iterate_nested called once per (n_outer, n_inner) chunk,
+    on one state and one p0 buffer."""
+    st = plan.new_state(c)
+    p0 = None
+    for n_outer, n_inner in chunks:
+        p0, _ = plan.mocca_iterate_nested(st, params, n_outer, n_inner, p0=p0)
+    torch.cuda.synchronize()
+    return st
+
+
+@pytest.mark.parametrize("precond,curvature", [("block", "clip"), ("diag", "window")])
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_nested_slots_equal_single_scan_nested(scans, precond, curvature, use_graph):
+    """Slots with 2 and 3 inner steps per expansion point beside single-loop
+    slots: each follows osscir_mocca_iterate_nested (or the single loop) bit
+    for bit; iters counts inner steps."""
+    from paper_1801_06263_amd import Batch, Params
+    modes = Params(1.0, precond, curvature, True)
+    b = Batch(modes, 8)
+    inner = [2, 3, 1, 2]
+    states = []
+    for i, ((pr, plan, c), k) in enumerate(zip(scans, inner)):
+        st = plan.new_state(c)
+        b.set_slot(i, plan, st, lam_of(pr), n_inner=k)
+        states.append(st)
+    n_it = 6
+    b.iterate(n_it, use_graph=use_graph)
+    status = b.status()
+    for i, ((pr, plan, c), k) in enumerate(zip(scans, inner)):
+        prm = Params(lam_of(pr), precond, curvature, True)
+        ref = nested_run(plan, c, prm, [(n_it // k, k)])
+        assert same_state(states[i], ref), (pr.name, k)
+        assert status[i][1] == n_it
+
+
+def test_nested_slot_stops_inside_an_outer_iteration(scans):
+    """max_iter = 6 with 4 inner steps: one whole outer iteration and the first
+    two steps of the next, as the single-scan calls (1 x 4) then (1 x 2)."""
+    from paper_1801_06263_amd import Batch, Params
+    from paper_1801_06263_amd.osscir import SLOT_DONE
+    pr, plan, c = scans[0]
+    modes = Params(1.0, "block", "clip", True)
+    b = Batch(modes, 4)
+    st = plan.new_state(c)
+    b.set_slot(0, plan, st, lam_of(pr), max_iter=6, n_inner=4)
+    b.iterate(9, use_graph=True)
+    assert b.status()[0][:2] == (SLOT_DONE, 6)
+    ref = nested_run(plan, c, Params(lam_of(pr), "block", "clip", True), [(1, 4), (1, 2)])
+    assert same_state(st, ref)
+
+
+def test_nesting_change_recaptures_and_tuning_keeps_p0(scans):
+    """Single-loop slots first (graph without the nested kernel variant), then a
+    nested slot bound between replays; tuning in the middle restores every
+    slot, p0 included."""
+    from paper_1801_06263_amd import Batch, Params
+    modes = Params(1.0, "block", "clip", True)
+    b = Batch(modes, 4)
+    (pr0, plan0, c0), (pr1, plan1, c1) = scans[0], scans[1]
+    s0 = plan0.new_state(c0)
+    b.set_slot(0, plan0, s0, lam_of(pr0))
+    b.iterate(2, use_graph=True)
+    s1 = plan1.new_state(c1)
+    b.set_slot(1, plan1, s1, lam_of(pr1), n_inner=3)
+    b.iterate(4, use_graph=True)
+    b.tune(1)
+    b.iterate(2, use_graph=True)
+    prm0 = Params(lam_of(pr0), "block", "clip", True)
+    prm1 = Params(lam_of(pr1), "block", "clip", True)
+    assert same_state(s0, single_run(plan0, c0, prm0, 8))
+    assert same_state(s1, nested_run(plan1, c1, prm1, [(2, 3)]))
+
+
+def test_nested_slot_argument_errors(scans):
+    from paper_1801_06263_amd import Batch, Params
+    from paper_1801_06263_amd.osscir import OsscirError, _lib, _stream_handle
+    import ctypes
+    pr, plan, c = scans[0]
+    b = Batch(Params(1.0), 2)
+    st = plan.new_state(c)
+    with pytest.raises(OsscirError, match="n_inner"):
+        b.set_slot(0, plan, st, lam_of(pr), n_inner=0)
+    cst = plan._c_state(st)
+    rc = _lib.osscir_batch_set_slot_nested(b._h, 0, plan._h, ctypes.byref(cst), 1e-7, 0, 0.0, 3, None,
+                                           _stream_handle(None))
+    assert rc == -1

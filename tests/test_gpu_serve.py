@@ -122,3 +122,37 @@ def test_served_request_matches_oracle(reqs):
         rel = np.linalg.norm(f[m] - ref.f[m]) / np.linalg.norm(ref.f[m])
         print(f"served tiny request, material {m}: rel L2 vs oracle {rel:.2e}")
         assert rel <= 1e-3
+
+
+def test_nested_request_served_among_single_loop_requests(reqs):
+    """A tiny-scan request with four inner steps per expansion point at a
+    lambda where the single loop diverges on this scan (1e-6), served among
+    single-loop requests: the same bits as osscir_mocca_iterate_nested alone,
+    and within 1e-3 of the oracle's nested loops."""
+    import dataclasses
+
+    from oracle import model, mocca, projector
+    from paper_1801_06263_amd import Params, Plan
+    from paper_1801_06263_amd.serve import Request
+    pr = synth.problem("tiny")
+    X = projector.system_matrix(pr.geom)
+    c = synth.poisson_counts(model.counts_model(X @ pr.f_true.reshape(3, -1).T, pr.spec), pr.seed)
+    lam, n_outer, n_inner = 1e-6, 10, 4
+    g = pr.geom
+    counts = np.ascontiguousarray(c.T.reshape(4, g.n_views, g.n_bins), dtype=np.float32)
+    mine = Request(98, g, pr.spec, counts, lam, max_iter=n_outer * n_inner, arrival=0.01, n_inner=n_inner)
+    others = [dataclasses.replace(r, arrival=0.005 * i) for i, r in enumerate(reqs[:5])]
+    mix, _ = run(others + [mine], max_slots=8, iters_per_tick=3)
+    res = mix[98]
+    assert res.iters == n_outer * n_inner
+    plan = Plan(g, pr.spec)
+    st = plan.new_state(torch.as_tensor(counts).cuda())
+    plan.mocca_iterate_nested(st, Params(lam, "block", "clip", True), n_outer, n_inner)
+    torch.cuda.synchronize()
+    assert torch.equal(st.f, res.f)
+    ref = mocca.mocca_nested(X, c, pr.spec, lam, n_outer, n_inner, "block", "clip")
+    f = host(res.f).reshape(3, -1)
+    for m in range(3):
+        rel = np.linalg.norm(f[m] - ref.f[m]) / np.linalg.norm(ref.f[m])
+        print(f"served nested request, material {m}: rel L2 vs oracle {rel:.2e}")
+        assert rel <= 1e-3
