@@ -418,3 +418,23 @@ def test_nested_slot_argument_errors(scans):
     rc = _lib.osscir_batch_set_slot_nested(b._h, 0, plan._h, ctypes.byref(cst), 1e-7, 0, 0.0, 3, None,
                                            _stream_handle(None))
     assert rc == -1
+
+
+def test_nested_slot_with_per_bin_spectra(scans):
+    """A nested slot whose scan has one response per detector bin (the per-bin
+    call of the batched kernel's nested variant) beside a single-loop slot."""
+    from paper_1801_06263_amd import Batch, Params, Plan
+    pr = synth.problem("tiny")
+    det = synth.make_detector_spectral(pr.geom.n_bins, 20, 119, 120.0, 1e5, 77)
+    plan = Plan(pr.geom, det)
+    c = lib_counts(plan, pr)
+    modes = Params(1.0, "block", "clip", True)
+    b = Batch(modes, 4)
+    st = plan.new_state(c)
+    b.set_slot(0, plan, st, 1e-6, n_inner=3)
+    pr1, plan1, c1 = scans[1]
+    s1 = plan1.new_state(c1)
+    b.set_slot(1, plan1, s1, lam_of(pr1))
+    b.iterate(6, use_graph=True)
+    assert same_state(st, nested_run(plan, c, Params(1e-6, "block", "clip", True), [(2, 3)]))
+    assert same_state(s1, single_run(plan1, c1, Params(lam_of(pr1), "block", "clip", True), 6))
