@@ -174,10 +174,33 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
 // directly, so the products and their order are exactly those of
 // forward_walk.
 //
+// The loop is rotated: once a step's candidates are in registers, the next
+// step's copies are issued and the step's products summed while they are in
+// flight (one LDS window per wave, as before).  Two register sets alternate
+// so nothing is moved between iterations.
+//
 // The source lies on a 2^-30-pixel grid (the plan rounds it there), so
-// every offset s - i is exact in FP64: the column offset steps by -1 and the
+// every offset s - i is exact in FP64: the column offset is s_u - u and the
 // second candidate's offset is the first's minus one, with the same bits as
 // the back-projector's per-pixel offsets.
+struct WalkStep {
+  int iv0s[kFpUnroll];   // first candidate row per column
+  int r0;                // first row of the step's window
+  bool via_lds;          // the window fits 64 rows
+  float w[kFpUnroll][2];
+  float4 fv[kFpUnroll][2];
+};
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// Marks loaded candidates as held in registers: without it the compiler
+// turns values carried into the next iteration back into loads at their use.
+__device__ __forceinline__ void hold(float4 &x) {
+  f32x4_t v = __builtin_bit_cast(f32x4_t, x);
+  asm volatile("" : "+v"(v));
+  x = __builtin_bit_cast(float4, v);
+}
+
 template <bool XMAJOR>
 __device__ __forceinline__ void forward_walk_lds(int lo, int hi, int n, const float4 *__restrict__ img, double s_u,
                                                  double s_v, float slope, float base, const RayLine &ray, double &s0,
@@ -192,68 +215,77 @@ __device__ __forceinline__ void forward_walk_lds(int lo, int hi, int n, const fl
   const int lane = (int)__lane_id();
   float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
   int pairs = 0;
-  double du0 = s_u - (double)lo;  // exact
-  for (int u = lo; u <= hi; u += kFpUnroll) {
-    int iv0s[kFpUnroll];
+  // the step at column u: candidate rows, window, and the window's copies
+  // (wb must be free: the previous step's reads have completed)
+  auto fetch = [&](int u, WalkStep &st) {
 #pragma unroll
     for (int k = 0; k < kFpUnroll; ++k) {
       const float ys = __fmaf_rn(slope, (float)(u + k), base);
-      iv0s[k] = floor_to_int(__builtin_amdgcn_fmed3f(ys, -2.0f, (float)n));  // in [-2, n]
+      st.iv0s[k] = floor_to_int(__builtin_amdgcn_fmed3f(ys, -2.0f, (float)n));  // in [-2, n]
     }
     // the step's rows r0 .. r0 + span - 1 (r0 >= -3, r0 + span - 1 <= n + 2)
-    const int c00 = __builtin_amdgcn_readlane(iv0s[0], 0), c01 = __builtin_amdgcn_readlane(iv0s[0], 63);
-    const int c30 = __builtin_amdgcn_readlane(iv0s[kFpUnroll - 1], 0);
-    const int c31 = __builtin_amdgcn_readlane(iv0s[kFpUnroll - 1], 63);
-    const int r0 = min(min(c00, c01), min(c30, c31)) - 1;
-    const int span = max(max(c00, c01), max(c30, c31)) - r0 + 3;
-    const bool via_lds = span <= 64;  // uniform
-    __builtin_amdgcn_s_waitcnt(0);    // the previous step's reads of wb have completed
-    if (via_lds && lane < span) {
-      const float4 *col = img + ((size_t)(u + kPad) * np + (r0 + kPad)) + lane;
+    const int c00 = __builtin_amdgcn_readlane(st.iv0s[0], 0), c01 = __builtin_amdgcn_readlane(st.iv0s[0], 63);
+    const int c30 = __builtin_amdgcn_readlane(st.iv0s[kFpUnroll - 1], 0);
+    const int c31 = __builtin_amdgcn_readlane(st.iv0s[kFpUnroll - 1], 63);
+    st.r0 = min(min(c00, c01), min(c30, c31)) - 1;
+    const int span = max(max(c00, c01), max(c30, c31)) - st.r0 + 3;
+    st.via_lds = span <= 64;  // uniform
+    if (st.via_lds && lane < span) {
+      const float4 *col = img + ((size_t)(u + kPad) * np + (st.r0 + kPad)) + lane;
 #pragma unroll
       for (int k = 0; k < kFpUnroll; ++k)
         __builtin_amdgcn_global_load_lds(col + (size_t)k * np, wb + k * 64, 16, 0, 0);
     }
-    float w[kFpUnroll][2];
+  };
+  auto weights = [&](int u, WalkStep &st) {
+    const double du0 = s_u - (double)u;  // exact
 #pragma unroll
     for (int k = 0; k < kFpUnroll; ++k) {
       const double du = du0 - (double)k;  // exact
-      const double dv0 = s_v - (double)iv0s[k];
-      const double dv1 = dv0 - 1.0;      // exact
+      const double dv0 = s_v - (double)st.iv0s[k];
+      const double dv1 = dv0 - 1.0;  // exact
       if (XMAJOR) {
-        w[k][0] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, du, dv0);
-        w[k][1] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, du, dv1);
+        st.w[k][0] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, du, dv0);
+        st.w[k][1] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, du, dv1);
       } else {
-        w[k][0] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, dv0, du);
-        w[k][1] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, dv1, du);
+        st.w[k][0] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, dv0, du);
+        st.w[k][1] = chord_weight(ray.nxk, ray.nyk, ray.ak, ray.hmax, dv1, du);
       }
     }
-    float4 fv[kFpUnroll][2];
-    __builtin_amdgcn_s_waitcnt(0);  // the copies have landed in LDS
-    if (via_lds) {
+  };
+  // after the copies have landed: the candidates
+  auto read = [&](int u, WalkStep &st) {
+    if (st.via_lds) {
       // generic view of the LDS rows (reads stay ds_read); slot of row r: r - r0
-      const float4 *wr = (const float4 *)wb - r0;
+      const float4 *wr = (const float4 *)wb - st.r0;
 #pragma unroll
       for (int k = 0; k < kFpUnroll; ++k) {
-        fv[k][0] = wr[k * 64 + iv0s[k]];
-        fv[k][1] = wr[k * 64 + iv0s[k] + 1];
+        st.fv[k][0] = wr[k * 64 + st.iv0s[k]];
+        st.fv[k][1] = wr[k * 64 + st.iv0s[k] + 1];
       }
     } else {
 #pragma unroll
       for (int k = 0; k < kFpUnroll; ++k) {
         const char *__restrict__ line = reinterpret_cast<const char *>(img + (size_t)(u + k + kPad) * np);
-        const unsigned o0 = (unsigned)(iv0s[k] + kPad) * 16u;
-        fv[k][0] = *reinterpret_cast<const float4 *>(line + o0);
-        fv[k][1] = *reinterpret_cast<const float4 *>(line + o0 + 16u);
+        const unsigned o0 = (unsigned)(st.iv0s[k] + kPad) * 16u;
+        st.fv[k][0] = *reinterpret_cast<const float4 *>(line + o0);
+        st.fv[k][1] = *reinterpret_cast<const float4 *>(line + o0 + 16u);
       }
     }
+#pragma unroll
+    for (int k = 0; k < kFpUnroll; ++k) {
+      hold(st.fv[k][0]);
+      hold(st.fv[k][1]);
+    }
+  };
+  auto sum = [&](const WalkStep &st) {
 #pragma unroll
     for (int k = 0; k < kFpUnroll; ++k)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        a0 = __fmaf_rn(w[k][j], fv[k][j].x, a0);
-        a1 = __fmaf_rn(w[k][j], fv[k][j].y, a1);
-        a2 = __fmaf_rn(w[k][j], fv[k][j].z, a2);
+        a0 = __fmaf_rn(st.w[k][j], st.fv[k][j].x, a0);
+        a1 = __fmaf_rn(st.w[k][j], st.fv[k][j].y, a1);
+        a2 = __fmaf_rn(st.w[k][j], st.fv[k][j].z, a2);
       }
     if (++pairs == 16 / kFpUnroll) {
       s0 += (double)a0;
@@ -262,7 +294,33 @@ __device__ __forceinline__ void forward_walk_lds(int lo, int hi, int n, const fl
       a0 = a1 = a2 = 0.0f;
       pairs = 0;
     }
-    du0 -= (double)kFpUnroll;
+  };
+  WalkStep A, B;
+  __builtin_amdgcn_s_waitcnt(0);
+  fetch(lo, A);
+  weights(lo, A);
+  __builtin_amdgcn_s_waitcnt(0);  // A's copies have landed
+  read(lo, A);
+  for (int u = lo;; u += 2 * kFpUnroll) {
+    // A holds step u; B takes step u + kFpUnroll
+    __builtin_amdgcn_s_waitcnt(0);  // A's candidates are in registers: wb is free
+    const bool nb = u + kFpUnroll <= hi;  // uniform
+    if (nb) fetch(u + kFpUnroll, B);
+    __builtin_amdgcn_sched_barrier(0);  // the copies go out before the sums
+    sum(A);
+    if (!nb) break;
+    weights(u + kFpUnroll, B);
+    __builtin_amdgcn_s_waitcnt(0);  // B's copies have landed
+    read(u + kFpUnroll, B);
+    __builtin_amdgcn_s_waitcnt(0);
+    const bool na = u + 2 * kFpUnroll <= hi;
+    if (na) fetch(u + 2 * kFpUnroll, A);
+    __builtin_amdgcn_sched_barrier(0);
+    sum(B);
+    if (!na) break;
+    weights(u + 2 * kFpUnroll, A);
+    __builtin_amdgcn_s_waitcnt(0);
+    read(u + 2 * kFpUnroll, A);
   }
   s0 += (double)a0;
   s1 += (double)a1;
