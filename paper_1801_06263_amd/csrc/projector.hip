@@ -28,17 +28,35 @@ __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ f, int n
 // view); two waves per workgroup measured faster than one or four.
 constexpr int kFpBlock = 128;
 
+// Workgroup -> (view v, bin chunk) of the forward projection.  XCD x takes
+// the views [x V / 8, (x + 1) V / 8), an arc whose rays mostly share one
+// major axis and hence one packed copy (see xcd_item), and walks it chunk
+// rank by chunk rank: the centre chunks of every view of the arc first, the
+// edge chunks last.  Central rays cross the most pixels, so the longest
+// workgroups are dispatched first and the last ones, which set the tail of
+// the launch, are the shortest.
+__device__ __forceinline__ bool forward_item(int n_views, int nchunk, int &v, int &chunk) {
+  const int b = blockIdx.x, x = b % kXcds, i = b / kXcds;
+  const int v0 = (int)((long long)x * n_views / kXcds);
+  const int nv = (int)((long long)(x + 1) * n_views / kXcds) - v0;
+  if (i >= nv * nchunk) return false;  // also every workgroup of an XCD without views
+  const int r = i / nv;                // chunk rank: 0 = centre
+  v = v0 + (i - r * nv);
+  const int mid = (nchunk - 1) / 2;
+  chunk = (r & 1) ? mid + ((r + 1) >> 1) : mid - (r >> 1);  // mid, mid + 1, mid - 1, mid + 2, ...
+  return true;
+}
+
 template <bool COUNT>
 __global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__restrict__ pk_xy,
                                                   const float4 *__restrict__ pk_yx, float *__restrict__ p,
                                                   int p_stride, int nch) {
   const int bs = blockDim.x;
   const int nchunk = (sd.n_bins + bs - 1) / bs;
-  int item;
-  if (!xcd_item(sd.n_views * nchunk, item)) return;
-  const int v = item / nchunk;
+  int v, chunk;
+  if (!forward_item(sd.n_views, nchunk, v, chunk)) return;
   __shared__ float4 fwd_lds[kFpBlock / 64][kFpUnroll * 64];  // 4 KB of image rows per wave
-  forward_rays<COUNT>(sd, pk_xy, pk_yx, p, p_stride, nch, v, (item - v * nchunk) * bs,
+  forward_rays<COUNT>(sd, pk_xy, pk_yx, p, p_stride, nch, v, chunk * bs,
                       (float4 OSSCIR_LDS *)fwd_lds[threadIdx.x >> 6]);
 }
 
@@ -81,9 +99,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
 
 // ----------------------------------------------------------------- launchers
 
+// workgroups of k_forward: the largest arc of views (forward_item) times the
+// bin chunks, on every XCD
 static unsigned forward_blocks(const ScanDesc &sd) {
-  const int items = sd.n_views * ((sd.n_bins + kFpBlock - 1) / kFpBlock);
-  return (unsigned)(((items + kXcds - 1) / kXcds) * kXcds);
+  const int nchunk = (sd.n_bins + kFpBlock - 1) / kFpBlock;
+  return (unsigned)(kXcds * ((sd.n_views + kXcds - 1) / kXcds) * nchunk);
 }
 
 size_t pack_scratch_bytes(const ScanDesc &sd) {
