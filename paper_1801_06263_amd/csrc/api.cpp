@@ -52,7 +52,7 @@ WorkLayout osscir::work_layout(const ScanDesc &sd) {
   return w;
 }
 
-std::vector<int> osscir::region_tile_order(int nt) {
+std::vector<int> osscir::region_tile_order(int nt, int cus_per_xcd) {
   std::vector<int> order;
   order.reserve((size_t)nt * nt);
   const int rb = (nt + 3) / 4, cb = (nt + 1) / 2;
@@ -60,7 +60,37 @@ std::vector<int> osscir::region_tile_order(int nt) {
     for (int half = 0; half < 2; ++half)
       for (int ty = band * rb; ty < std::min(nt, (band + 1) * rb); ++ty)
         for (int tx = half * cb; tx < std::min(nt, (half + 1) * cb); ++tx) order.push_back(ty * nt + tx);
-  return order;
+  if (cus_per_xcd < 1) return order;
+  // Balanced for one launch of every tile: a tile's window work over a full
+  // orbit grows with its distance from the rotation centre (the outer tiles
+  // pass closer to the source, where their shadows are wider; at 512^2 the
+  // corner tiles have 1.2x the mean work and the centre ones 0.88x).  The
+  // eighths become sectors around the centre (tiles by angle), so every XCD
+  // gets the same mix of radii, and within an eighth the tiles at positions
+  // congruent modulo the XCD's CU count, which one CU receives, are dealt
+  // in a snake over the tiles ranked by radius: each CU takes one tile from
+  // every row of ranks, heavy and light alike.
+  const int S = cus_per_xcd, n = nt * nt, per = (n + kXcds - 1) / kXcds;
+  const double c = 0.5 * nt;
+  auto r2 = [&](int t) {
+    const double dx = (t % nt) + 0.5 - c, dy = (t / nt) + 0.5 - c;
+    return dx * dx + dy * dy;
+  };
+  auto angle = [&](int t) { return std::atan2((t / nt) + 0.5 - c, (t % nt) + 0.5 - c); };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return angle(a) < angle(b); });
+  std::vector<int> out(order);
+  for (int x0 = 0; x0 < n; x0 += per) {
+    const int m = std::min(per, n - x0);
+    std::vector<int> rank(order.begin() + x0, order.begin() + x0 + m);
+    std::stable_sort(rank.begin(), rank.end(), [&](int a, int b) { return r2(a) > r2(b); });
+    for (int r = 0; r < m; ++r) {
+      const int q = r / S, k = r % S;
+      const bool full_row = (q + 1) * S <= m;  // a partial last row keeps its order (its positions stay below m)
+      const int g = (q % 2 == 1 && full_row) ? S - 1 - k : k;
+      out[x0 + q * S + g] = rank[r];
+    }
+  }
+  return out;
 }
 
 int osscir::check_plan(osscir_plan plan) {
@@ -278,7 +308,9 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
       n0ray[l] = make_float4((float)n0[0], (float)n0[1], (float)n0[2], (float)n0[3]);
     }
   }
-  const std::vector<int> tiles = region_tile_order((N + kBpTile - 1) / kBpTile);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1) cus = 256;
+  const std::vector<int> tiles = region_tile_order((N + kBpTile - 1) / kBpTile, std::max(1, cus / kXcds));
   hipError_t e;
   if ((e = hipMalloc(&p->d_rays, rays.size() * sizeof(RayLine))) != hipSuccess ||
       (e = hipMalloc(&p->d_views, views.size() * sizeof(ViewGeom))) != hipSuccess ||
@@ -357,8 +389,6 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   // four workgroups per CU (measured: 4% faster at 1024 tiles on 256 CUs,
   // 8-10% slower at 256 tiles and fewer)
   {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1) cus = 256;
     const int nt = (N + kBpTile - 1) / kBpTile;
     sd.bp_copy = nt * nt >= 4 * cus ? 1 : 0;
   }

@@ -54,8 +54,11 @@ WorkLayout work_layout(const ScanDesc &sd);
 // The 16 x 16 back-projection tiles (index ty * nt + tx) in region order:
 // the image split into 4 bands of rows x 2 halves of columns, regions one
 // after the other, row-major inside; consecutive eighths of this order are
-// compact blocks of the image (one per XCD).
-std::vector<int> region_tile_order(int nt);
+// compact blocks of the image (one per XCD).  cus_per_xcd > 0 (one launch
+// of every tile): the eighths are instead sectors around the image centre,
+// each re-dealt so that the tiles one CU receives (positions congruent
+// modulo cus_per_xcd) mix outer and inner tiles.
+std::vector<int> region_tile_order(int nt, int cus_per_xcd = 0);
 
 // The per-view sources and per-ray line parameters of a (validated) geometry.
 void build_ray_table(const osscir_geometry &g, std::vector<RayLine> &rays, std::vector<ViewGeom> &views);
