@@ -58,14 +58,15 @@ __device__ __forceinline__ bool slot_running(const SlotStatus *status, int s) {
   return as_const(status)[s].state == kSlotRunning;
 }
 
-__global__ void __launch_bounds__(256, 6) kb_forward(const SlotDesc *__restrict__ slots,
-                                                   const SlotStatus *__restrict__ status, WorkList wl) {
+__global__ void __launch_bounds__(256 * kFpParts, 6 / kFpParts) kb_forward(const SlotDesc *__restrict__ slots,
+                                                                       const SlotStatus *__restrict__ status,
+                                                                       WorkList wl) {
   const int x = blockIdx.x % kXcds;
   const int stride = gridDim.x / kXcds;
   const int cnt = list_count(wl, x);
-  const int R = blockDim.x;
-  extern __shared__ float4 fwd_rows[];  // kFpUnroll x 64 image rows per wave (forward_walk_lds)
-  float4 OSSCIR_LDS *wb = (float4 OSSCIR_LDS *)(fwd_rows + (threadIdx.x >> 6) * (kFpUnroll * 64));
+  const int R = blockDim.x / kFpParts;  // rays per item
+  extern __shared__ float4 fwd_rows[];  // kFpWaveRows image rows per wave (forward_walk_lds)
+  float4 OSSCIR_LDS *wb = (float4 OSSCIR_LDS *)(fwd_rows + (threadIdx.x >> 6) * kFpWaveRows);
   for (int j = blockIdx.x / kXcds; j < cnt; j += stride) {
     const int it = list_item(wl, x, j);
     const int s = item_slot(it), local = item_local(it);
@@ -177,8 +178,9 @@ __global__ void __launch_bounds__(64) kb_tick(const SlotDesc *__restrict__ slots
 
 hipError_t launch_batch_forward(const SlotDesc *slots, const SlotStatus *status, WorkList wl, int rays_per_wg,
                                 hipStream_t st) {
-  const size_t lds = (size_t)(rays_per_wg / 64) * kFpUnroll * 64 * sizeof(float4);
-  hipLaunchKernelGGL(kb_forward, dim3((unsigned)wl.wgs), dim3((unsigned)rays_per_wg), lds, st, slots, status, wl);
+  const int threads = rays_per_wg * kFpParts;  // kFpParts waves per 64 rays
+  const size_t lds = (size_t)(threads / 64) * kFpWaveRows * sizeof(float4);
+  hipLaunchKernelGGL(kb_forward, dim3((unsigned)wl.wgs), dim3((unsigned)threads), lds, st, slots, status, wl);
   return hipGetLastError();
 }
 

@@ -25,8 +25,10 @@ __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ f, int n
 }
 
 // Rays per forward-projection workgroup (a chunk of consecutive bins of one
-// view); two waves per workgroup measured faster than one or four.
-constexpr int kFpBlock = 128;
+// view), each walked by kFpParts waves: two waves per workgroup measured
+// faster than one or four.
+constexpr int kFpRays = 64;
+constexpr int kFpBlock = kFpRays * kFpParts;  // threads
 
 // Workgroup -> (view v, bin chunk) of the forward projection.  XCD x takes
 // the views [x V / 8, (x + 1) V / 8), an arc whose rays mostly share one
@@ -51,12 +53,11 @@ template <bool COUNT>
 __global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__restrict__ pk_xy,
                                                   const float4 *__restrict__ pk_yx, float *__restrict__ p,
                                                   int p_stride, int nch) {
-  const int bs = blockDim.x;
-  const int nchunk = (sd.n_bins + bs - 1) / bs;
+  const int nchunk = (sd.n_bins + kFpRays - 1) / kFpRays;
   int v, chunk;
-  if (!forward_item(sd.n_views, nchunk, v, chunk)) return;
-  __shared__ float4 fwd_lds[kFpBlock / 64][kFpUnroll * 64];  // 4 KB of image rows per wave
-  forward_rays<COUNT>(sd, pk_xy, pk_yx, p, p_stride, nch, v, chunk * bs,
+  if (!forward_item(sd.n_views, nchunk, v, chunk)) return;  // uniform over the workgroup
+  __shared__ float4 fwd_lds[kFpBlock / 64][kFpWaveRows];  // 4 KB of image rows per wave
+  forward_rays<COUNT>(sd, pk_xy, pk_yx, p, p_stride, nch, v, chunk * kFpRays,
                       (float4 OSSCIR_LDS *)fwd_lds[threadIdx.x >> 6]);
 }
 
@@ -102,7 +103,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
 // workgroups of k_forward: the largest arc of views (forward_item) times the
 // bin chunks, on every XCD
 static unsigned forward_blocks(const ScanDesc &sd) {
-  const int nchunk = (sd.n_bins + kFpBlock - 1) / kFpBlock;
+  const int nchunk = (sd.n_bins + kFpRays - 1) / kFpRays;
   return (unsigned)(kXcds * ((sd.n_views + kXcds - 1) / kXcds) * nchunk);
 }
 
