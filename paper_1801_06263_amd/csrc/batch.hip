@@ -58,7 +58,7 @@ __device__ __forceinline__ bool slot_running(const SlotStatus *status, int s) {
   return as_const(status)[s].state == kSlotRunning;
 }
 
-__global__ void __launch_bounds__(256 * kFpParts, 6 / kFpParts) kb_forward(const SlotDesc *__restrict__ slots,
+__global__ void __launch_bounds__(256 * kFpParts) __attribute__((amdgpu_waves_per_eu(5))) kb_forward(const SlotDesc *__restrict__ slots,
                                                                        const SlotStatus *__restrict__ status,
                                                                        WorkList wl) {
   const int x = blockIdx.x % kXcds;

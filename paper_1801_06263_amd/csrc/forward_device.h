@@ -331,8 +331,9 @@ __device__ __forceinline__ void forward_walk_lds(int lo, int hi, int n, const fl
 // columns, and the parts' FP64 sums are added in part order.  A central ray
 // crosses ~500 columns and an edge one a few dozen, so a whole-ray wave
 // lives for a large share of the launch and the last ones dispatched set its
-// tail; parts halve that (the forward projection took 0.37 -> 0.32 ms).
-constexpr int kFpParts = 2;
+// tail; parts shorten that (measured at 512^2: 0.376 ms whole, 0.313 / 0.290
+// / 0.282 ms with 2 / 3 / 4 parts; 6 and 8 parts were slower again).
+constexpr int kFpParts = 4;
 constexpr int kFpWaveRows = kFpUnroll * 64;  // float4 rows of LDS per wave (forward_walk_lds)
 
 // One workgroup: rays (v, d0 + 64 g + lane) of one view, g = wave / kFpParts,

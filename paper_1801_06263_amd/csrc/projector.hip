@@ -25,8 +25,7 @@ __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ f, int n
 }
 
 // Rays per forward-projection workgroup (a chunk of consecutive bins of one
-// view), each walked by kFpParts waves: two waves per workgroup measured
-// faster than one or four.
+// view), each walked by kFpParts waves.
 constexpr int kFpRays = 64;
 constexpr int kFpBlock = kFpRays * kFpParts;  // threads
 
@@ -50,7 +49,7 @@ __device__ __forceinline__ bool forward_item(int n_views, int nchunk, int &v, in
 }
 
 template <bool COUNT>
-__global__ void __launch_bounds__(256) k_forward(ScanDesc sd, const float4 *__restrict__ pk_xy,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_forward(ScanDesc sd, const float4 *__restrict__ pk_xy,
                                                   const float4 *__restrict__ pk_yx, float *__restrict__ p,
                                                   int p_stride, int nch) {
   const int nchunk = (sd.n_bins + kFpRays - 1) / kFpRays;
