@@ -166,7 +166,7 @@ __device__ __forceinline__ void forward_walk(int lo, int hi, int n, const float4
 // over a step of kFpUnroll columns the candidate rows of the wave's 64 rays
 // lie between the crossings of its first and last lanes at the step's first
 // and last columns.  The step copies that window of rows (one row per lane,
-// 16-byte global-to-LDS loads from a scalar base: no VGPRs, one copy of a
+// 16-byte buffer-to-LDS loads from a scalar offset: no VGPRs, one copy of a
 // pixel that neighbouring rays share) for each of its columns, and each lane
 // reads its two candidates per column from LDS.  The window keeps one row of
 // margin on each side for crossings that FP32 rounding moves across a row
@@ -193,6 +193,20 @@ struct WalkStep {
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
+// min / max of wave-uniform values on the scalar unit (left to itself the
+// compiler forms them with vector min3 / max3 and moves them back, seven
+// vector instructions per step of a walk bound by vector issue)
+__device__ __forceinline__ int uniform_min(int a, int b) {
+  int r;
+  asm volatile("s_min_i32 %0, %1, %2" : "=s"(r) : "s"(a), "s"(b) : "scc");
+  return r;
+}
+__device__ __forceinline__ int uniform_max(int a, int b) {
+  int r;
+  asm volatile("s_max_i32 %0, %1, %2" : "=s"(r) : "s"(a), "s"(b) : "scc");
+  return r;
+}
+
 // Marks loaded candidates as held in registers: without it the compiler
 // turns values carried into the next iteration back into loads at their use.
 __device__ __forceinline__ void hold(float4 &x) {
@@ -213,6 +227,15 @@ __device__ __forceinline__ void forward_walk_lds(int lo, int hi, int n, const fl
   if (lo > hi) return;
   const int np = n + 2 * kPad;
   const int lane = (int)__lane_id();
+  // The copies go through a buffer descriptor of the packed image: the
+  // lane's 16-byte row offset is fixed, the column's offset is a scalar, and
+  // the wave's rows are a scalar LDS address, so forming a step's copies
+  // takes no vector instructions (the walk is bound by VALU issue).  Every
+  // copied row lies inside the padded image, the descriptor's range.
+  wb = (float4 OSSCIR_LDS *)(size_t)__builtin_amdgcn_readfirstlane((unsigned)(size_t)wb);
+  const __amdgpu_buffer_rsrc_t img_rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void *)img, 0, np * np * (int)sizeof(float4), kBufferRsrcWord3);
+  const unsigned lane_off = (unsigned)lane * 16u;  // this lane's row of a copied window
   float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
   int pairs = 0;
   // the step at column u: candidate rows, window, and the window's copies
@@ -227,14 +250,16 @@ __device__ __forceinline__ void forward_walk_lds(int lo, int hi, int n, const fl
     const int c00 = __builtin_amdgcn_readlane(st.iv0s[0], 0), c01 = __builtin_amdgcn_readlane(st.iv0s[0], 63);
     const int c30 = __builtin_amdgcn_readlane(st.iv0s[kFpUnroll - 1], 0);
     const int c31 = __builtin_amdgcn_readlane(st.iv0s[kFpUnroll - 1], 63);
-    st.r0 = min(min(c00, c01), min(c30, c31)) - 1;
-    const int span = max(max(c00, c01), max(c30, c31)) - st.r0 + 3;
+    st.r0 = uniform_min(uniform_min(c00, c01), uniform_min(c30, c31)) - 1;
+    const int span = uniform_max(uniform_max(c00, c01), uniform_max(c30, c31)) - st.r0 + 3;
     st.via_lds = span <= 64;  // uniform
     if (st.via_lds && lane < span) {
-      const float4 *col = img + ((size_t)(u + kPad) * np + (st.r0 + kPad)) + lane;
+      // a uniform base per column plus the lane's 16-byte row offset
+      const unsigned col = (unsigned)((u + kPad) * np + (st.r0 + kPad)) * (unsigned)sizeof(float4);  // uniform
 #pragma unroll
       for (int k = 0; k < kFpUnroll; ++k)
-        __builtin_amdgcn_global_load_lds(col + (size_t)k * np, wb + k * 64, 16, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(img_rsrc, (void OSSCIR_LDS *)(wb + k * 64), 16, lane_off,
+                                                 col + (unsigned)(k * np) * (unsigned)sizeof(float4), 0, 0);
     }
   };
   auto weights = [&](int u, WalkStep &st) {

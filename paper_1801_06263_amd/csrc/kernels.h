@@ -114,6 +114,10 @@ __device__ __forceinline__ bool xcd_item(int nitems, int &item) {
 #define OSSCIR_CONST __attribute__((address_space(4)))
 // Pointers into LDS (the destination of global-to-LDS loads).
 #define OSSCIR_LDS __attribute__((address_space(3)))
+// Last word of a raw buffer descriptor on gfx9-family GPUs (32-bit data
+// format, no swizzle): loads through it read bytes [0, num_records) of the
+// base address, with the offsets the instruction gives.
+constexpr int kBufferRsrcWord3 = 0x00020000;
 
 template <typename T>
 __device__ __forceinline__ const OSSCIR_CONST T *as_const(const T *p) {
