@@ -335,8 +335,16 @@ int osscir_batch_create(const osscir_params *modes, int32_t max_slots, osscir_ba
 /* Synchronises the device and frees the batch (not the plans or states). */
 int osscir_batch_destroy(osscir_batch batch);
 
-/* Bind scan `plan` with caller state `state` (as for osscir_mocca_iterate;
- * its buffers must stay allocated until the slot is cleared or rebound) and
+/* Bytes of device scratch a batch slot of this plan needs (host
+ * out-parameter): the iteration workspace without the region where the
+ * single-scan back-projection of a scan with few 16 x 16 tiles leaves its
+ * per-part sums (the batched kernels form the same sums in registers), so at
+ * most osscir_workspace_bytes. */
+int osscir_batch_workspace_bytes(osscir_plan plan, size_t *bytes);
+
+/* Bind scan `plan` with caller state `state` (as for osscir_mocca_iterate,
+ * with work_bytes >= osscir_batch_workspace_bytes; its buffers must stay
+ * allocated until the slot is cleared or rebound) and
  * step ratio lambda to slot `slot`, replacing what was bound there, with the
  * stopping rule (max_iter, tol).  Enqueues the packing of state->fbar on
  * stream; the slot starts running with the next osscir_batch_iterate.  The

@@ -48,7 +48,9 @@ WorkLayout osscir::work_layout(const ScanDesc &sd) {
   w.qS = align256(w.p + 3 * L * sizeof(float));
   w.partial = align256(w.qS + 12 * L * sizeof(float));
   w.pack = align256(w.partial + (size_t)dtpl_partial_count(sd) * sizeof(double));
-  w.total = align256(w.pack + pack_scratch_bytes(sd));
+  w.bp = align256(w.pack + pack_scratch_bytes(sd));
+  const size_t bp_bytes = sd.bp_parts > 1 ? (size_t)sd.bp_parts * 9 * (size_t)sd.n * sd.n * sizeof(double) : 0;
+  w.total = align256(w.bp + bp_bytes);
   return w;
 }
 
@@ -388,9 +390,26 @@ int osscir_plan_create(const osscir_geometry *geom, const osscir_spectral *spec,
   // global-to-LDS staging in the fused back-projection when the tiles fill
   // four workgroups per CU (measured: 4% faster at 1024 tiles on 256 CUs,
   // 8-10% slower at 256 tiles and fewer)
+  // A grid of at most two tiles per CU leaves the CUs nearly empty (one
+  // 16 x 16 tile is four waves): its views are then split into parts, one
+  // workgroup per (tile, part), aiming at four workgroups per CU; a part is
+  // a whole number of 8-view FP32 flushes.  Global-to-LDS staging in the
+  // fused back-projection when the workgroups fill four per CU (measured:
+  // 4% faster at 1024 tiles on 256 CUs, 8-10% slower at 256 tiles and fewer).
   {
-    const int nt = (N + kBpTile - 1) / kBpTile;
-    sd.bp_copy = nt * nt >= 4 * cus ? 1 : 0;
+    const int nt = (N + kBpTile - 1) / kBpTile, tiles = nt * nt;
+    sd.bp_parts = 1;
+    sd.bp_part_views = V;
+    if (!sd.bp_wide && tiles <= 2 * cus) {
+      const int want = (4 * cus + tiles - 1) / tiles;
+      const int vp = ((V + want - 1) / want + 7) / 8 * 8;
+      const int parts = (V + vp - 1) / vp;
+      if (parts > 1) {
+        sd.bp_parts = parts;
+        sd.bp_part_views = vp;
+      }
+    }
+    sd.bp_copy = tiles * sd.bp_parts >= 4 * cus ? 1 : 0;
   }
   sd.rays = p->d_rays;
   sd.views = p->d_views;
@@ -481,6 +500,12 @@ int osscir_workspace_bytes(osscir_plan plan, size_t *bytes) {
   return OSSCIR_OK;
 }
 
+int osscir_batch_workspace_bytes(osscir_plan plan, size_t *bytes) {
+  if (!plan || !bytes) return fail(OSSCIR_EINVAL, "null argument");
+  *bytes = work_layout(plan->sd).bp;  // everything before the split back-projection's region
+  return OSSCIR_OK;
+}
+
 int osscir_ray_lengths(osscir_plan plan, float *rho, osscir_stream stream) {
   int rc = check_plan(plan);
   if (rc) return rc;
@@ -546,6 +571,7 @@ namespace {
 struct IterArgs {
   float *p, *qS;
   double *partial;
+  double *bp;  // split back-projection sums (bp_parts > 1)
   void *pack;
   bool block, clip, fp64;
   float lam;
@@ -570,6 +596,7 @@ int check_iter(osscir_plan plan, const osscir_params *params, const osscir_state
   out->qS = (float *)((char *)state->work + wl.qS);
   out->partial = (double *)((char *)state->work + wl.partial);
   out->pack = (char *)state->work + wl.pack;
+  out->bp = (double *)((char *)state->work + wl.bp);
   out->block = params->precond == OSSCIR_PRECOND_BLOCK;
   out->clip = params->curvature == OSSCIR_CURV_CLIP;
   out->fp64 = params->fp64_small != 0;
@@ -594,7 +621,8 @@ int run_stage(const ScanDesc &sd, const IterArgs &a, osscir_state *state, int st
                  "mocca: spectral model and dual step");
       break;
     case 2:
-      OSSCIR_HIP(launch_back_primal(sd, a.qS, state->f, state->fbar, a.lam, a.block, pack_next ? a.pack : nullptr, st),
+      OSSCIR_HIP(launch_back_primal(sd, a.qS, state->f, state->fbar, a.lam, a.block, pack_next ? a.pack : nullptr, a.bp,
+                                    st),
                  "mocca: back-projection and primal step");
       break;
     default:

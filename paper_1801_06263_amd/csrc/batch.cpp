@@ -416,8 +416,8 @@ int osscir_batch_set_slot_nested(osscir_batch b, int32_t slot, osscir_plan plan,
   if (n_inner < 1) return fail(OSSCIR_EINVAL, "nested: need n_inner >= 1 (got %d)", n_inner);
   if (n_inner > 1 && !p0) return fail(OSSCIR_EINVAL, "nested: null p0");
   const WorkLayout wl = work_layout(plan->sd);
-  if (state->work_bytes < wl.total)
-    return fail(OSSCIR_ESTATE, "workspace %zu < %zu bytes", state->work_bytes, wl.total);
+  if (state->work_bytes < wl.bp)  // the batch does not use the split back-projection's region
+    return fail(OSSCIR_ESTATE, "workspace %zu < %zu bytes", state->work_bytes, wl.bp);
   HostSlot &hs = b->slots[slot];
   hs.bound = true;
   hs.plan = plan;

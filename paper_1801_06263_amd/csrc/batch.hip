@@ -141,8 +141,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
     const int ntx = (sl.sd.n + kBpTile - 1) / kBpTile;
     const int ty = local / ntx, tx = local - ty * ntx;
     const PrimalEpilogue epi{sl.pk_xy, sl.pk_yx, partial + sl.first_tile + local};
-    // the persistent grid keeps four workgroups per CU: global-to-LDS staging
-    back_primal_tile<BLOCK, WIDE, true, !WIDE>(sl.sd, sl.qS, sl.f, sl.fbar, sl.lambda, tx, ty, sh, epi);
+    // the persistent grid keeps four workgroups per CU: global-to-LDS staging;
+    // the sums formed part by part, as the scan's own split back-projection
+    // forms them
+    back_primal_tile<BLOCK, WIDE, true, !WIDE, true>(sl.sd, sl.qS, sl.f, sl.fbar, sl.lambda, tx, ty, sh, epi);
   }
 }
 

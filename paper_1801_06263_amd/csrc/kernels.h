@@ -76,13 +76,16 @@ struct ScanDesc {
   float cbin;        // (n_bins - 1) / 2
   float n0[kWin];    // incident counts per window
   int bp_wide;       // some 16x16-tile shadow exceeds the back-projector's staging buffer
-  int bp_copy;       // enough tiles for four workgroups per CU: the fused step stages by global-to-LDS copies
+  int bp_copy;       // enough workgroups for four per CU: the fused step stages by global-to-LDS copies
+  int bp_parts;      // the fused back-projection's views split over this many workgroups per tile (grids of few
+                     // tiles), their FP64 sums added in order; 1: one workgroup per tile
+  int bp_part_views; // views per part: a multiple of 8 (n_views when bp_parts == 1)
   int per_bin;       // window responses and incident counts per detector bin
   int mfma;          // energy sums on the matrix cores (shared table, fits LDS)
   const float4 *sbin;   // [I][D] s_{w,d,i} (w = x, y, z, w), per_bin only
   const float4 *n0bin;  // [D] incident counts per window, per_bin only
   const float4 *n0ray;  // [L] incident counts per window of every ray (replaces n0 / n0bin), or null
-  const int *tile_order;  // [nt * nt] back-projection tiles (ty * nt + tx) in region order
+  const int *tile_order;  // [nt * nt] back-projection tiles (ty * nt + tx) in launch order (region_tile_order)
   const TileBins *tile_bins;  // [nt * nt][V] staged bins per (tile, view); null on the wide path
   const float4 *zero;     // 256 bytes of zeros (a null ray record and null inputs)
   const struct RayLine *rays;  // [L]

@@ -45,9 +45,10 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Caller workspace regions: p [3][L] f32 | qS [L][12] f32 (q and the step
 // terms interleaved per ray; planar scratch for the standalone step calls) |
-// partial sums (f64) | packed images of the forward projector.
+// partial sums (f64) | packed images of the forward projector | with
+// bp_parts > 1, the split back-projection's sums [part][9][n * n] f64.
 struct WorkLayout {
-  size_t p = 0, qS = 0, partial = 0, pack = 0, total = 0;
+  size_t p = 0, qS = 0, partial = 0, pack = 0, bp = 0, total = 0;  // bp: split back-projection sums (bp_parts > 1)
 };
 WorkLayout work_layout(const ScanDesc &sd);
 

@@ -400,10 +400,16 @@ __device__ __forceinline__ void load_soa(const BpSoa &S, int u, int idx, BinLDS 
 // are staged through registers into 80-byte records (two barriers per
 // group).  Both stagings hold the same records and sum them in the same
 // order, so they give the same bits.
-template <int NCH, bool QS12, bool COPY>
+// Views vb .. ve - 1 (vb a multiple of kBpFlush).  FOLD: the sum is formed
+// part by part, a part being bp_part_views consecutive views from view 0:
+// each part's FP64 sum starts from zero and the parts are added in order, so
+// the result has the bits of the split back-projection, whose workgroups sum
+// one part each (acc = ((p0 + p1) + p2) + ...; with one part, acc = 0 + p0 =
+// p0 exactly).
+template <int NCH, bool QS12, bool COPY, bool FOLD = false>
 __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int tile_x, int tile_y,
                                                         const float *__restrict__ q, int q_stride_i, double acc[NCH],
-                                                        BpShared &sh) {
+                                                        BpShared &sh, int vb, int ve) {
   static_assert(QS12 || !COPY, "global-to-LDS staging reads qS");
   static_assert(kBpGroup == 4 && kBpGroup * 64 == kBpThreads && kBpSlot == 64, "one wave per view, one lane per bin");
   static_assert(kBpFlush % kBpGroup == 0, "flushes at group ends");
@@ -412,7 +418,7 @@ __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int 
   bp_pixel_of_thread(tid, tx, ty);
   const int ix = tile_x * kBpTile + tx;
   const int iy = tile_y * kBpTile + ty;
-  const int V = sd.n_views;
+  const int V = ve;  // views past ve are not this call's
   const int nt = (sd.n + kBpTile - 1) / kBpTile;
   const unsigned nb = (unsigned)sd.n_bins, q_stride = (unsigned)q_stride_i;
   const float X = (float)ix - sd.c0;  // centred, for the detector projection
@@ -420,22 +426,27 @@ __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int 
   const float sid = in_vgpr(sd.sid_px);
   const double fx = (double)ix, fy = (double)iy;
   const int su = __builtin_amdgcn_readfirstlane(tid >> 6), sl = tid & 63;  // staged slot: view su, bin sl
-  const TileBins *__restrict__ tbs = sd.tile_bins + (size_t)(tile_y * nt + tile_x) * V;
+  const TileBins *__restrict__ tbs = sd.tile_bins + (size_t)(tile_y * nt + tile_x) * sd.n_views;
 #pragma unroll
   for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
+  double done[FOLD ? NCH : 1];  // FOLD: the parts before the current one
+#pragma unroll
+  for (int c = 0; c < (FOLD ? NCH : 1); ++c) done[c] = 0.0;
+  const int vp = FOLD ? sd.bp_part_views : V;
   float part[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) part[c] = 0.0f;
   BinRegs<NCH> nxt;
   {
-    const TileBins tb = load_uniform(tbs + min(su, V - 1));
+    const int j = vb + su;
+    const TileBins tb = load_uniform(tbs + min(j, V - 1));
     if (COPY)
-      copy_group_view(sd, q, nb, tb, su, su < V, su, sl, sh.soa[0]);
+      copy_group_view(sd, q, nb, tb, j, j < V, su, sl, sh.soa[0]);
     else
-      group_load<NCH, QS12>(sd, q, q_stride, nb, tb, su, su < V, sl, nxt);
+      group_load<NCH, QS12>(sd, q, q_stride, nb, tb, j, j < V, sl, nxt);
   }
   int buf = 0;
-  for (int g0 = 0; g0 < V; g0 += kBpGroup) {
+  for (int g0 = vb; g0 < V; g0 += kBpGroup) {
     if (COPY) {
       __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of the group have landed
       __syncthreads();                // every wave's have; the other buffer's reads are done
@@ -504,8 +515,19 @@ __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int 
         acc[c] += (double)part[c];
         part[c] = 0.0f;
       }
+      if (FOLD && (g0 + kBpGroup) % vp == 0 && g0 + kBpGroup < V) {  // uniform
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          done[c] += acc[c];
+          acc[c] = 0.0;
+        }
+      }
     }
     buf ^= 1;
+  }
+  if (FOLD) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = done[c] + acc[c];
   }
   __syncthreads();  // every wave is done with the staging buffers, which epilogues reuse
 }
@@ -514,15 +536,17 @@ __device__ __forceinline__ void back_accumulate_grouped(const ScanDesc &sd, int 
 // grouped variants give the same bits; the copies pay off when four
 // workgroups share a CU (the next group's copies then overlap other
 // workgroups' sums), register staging when the grid is small.
-template <int NCH, bool WIDE, bool QS12 = false, bool COPY = false>
+// Views vb .. ve - 1 (the grouped path; the wide path always takes every
+// view, and its plans have one part).
+template <int NCH, bool WIDE, bool QS12 = false, bool COPY = false, bool FOLD = false>
 __device__ __forceinline__ void back_accumulate(const ScanDesc &sd, int tile_x, int tile_y, const float *__restrict__ q,
-                                                int q_stride_i, double acc[NCH], BpShared &sh) {
+                                                int q_stride_i, double acc[NCH], BpShared &sh, int vb, int ve) {
   static_assert(NCH >= 1 && NCH <= 9, "1..9 channels");
   static_assert(QS12 || !COPY, "global-to-LDS staging reads qS");
   if (WIDE)
     back_accumulate_views<NCH, QS12>(sd, tile_x, tile_y, q, q_stride_i, acc, sh);
   else
-    back_accumulate_grouped<NCH, QS12, COPY>(sd, tile_x, tile_y, q, q_stride_i, acc, sh);
+    back_accumulate_grouped<NCH, QS12, COPY, FOLD>(sd, tile_x, tile_y, q, q_stride_i, acc, sh, vb, ve);
 }
 
 }  // namespace osscir

@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
   const int t = as_const(sd.tile_order)[item];
   const int tile_y = t / nt, tile_x = t - tile_y * nt;
   double acc[NCH];
-  back_accumulate<NCH, WIDE>(sd, tile_x, tile_y, q, q_stride, acc, sh);
+  back_accumulate<NCH, WIDE>(sd, tile_x, tile_y, q, q_stride, acc, sh, 0, sd.n_views);
   int tx, ty;
   bp_pixel_of_thread(threadIdx.x, tx, ty);
   const int ix = tile_x * kBpTile + tx;

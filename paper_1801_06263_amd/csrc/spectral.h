@@ -18,9 +18,11 @@ hipError_t launch_spectral_dual(const ScanDesc &sd, const float *p, const float 
 
 // back-projection of qS fused with the primal step and the extrapolation;
 // pack (optional): packed images (launch_pack's layout, borders already
-// zero) that receive fbar' for the next forward projection.
+// zero) that receive fbar' for the next forward projection; bp: the split
+// back-projection's sums (the workspace's bp region; needed when
+// sd.bp_parts > 1).
 hipError_t launch_back_primal(const ScanDesc &sd, const float *qS, float *f, float *fbar, float lambda, bool block,
-                              void *pack, hipStream_t st);
+                              void *pack, double *bp, hipStream_t st);
 
 // sigma [4][L], per-ray terms (scratch, 6 or 3 channels) and the pixel
 // steps out_img (T^-1 upper triangles or tau).

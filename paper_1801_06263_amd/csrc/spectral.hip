@@ -148,6 +148,65 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
                                             PrimalEpilogue{pk_xy, pk_yx, nullptr});
 }
 
+// Split back-projection (ScanDesc::bp_parts > 1, grids of few tiles): the
+// workgroup of (tile, part) sums the tile's pixels over the part's views and
+// leaves the FP64 sums in bp[part][c][pixel]; k_primal_combine adds the
+// parts in order and takes the primal step.  The one-workgroup-per-tile
+// kernels form the same sums part by part (FOLD), so every path gives the
+// same bits.
+template <bool BLOCK, bool COPY>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_back_partial(ScanDesc sd, const float *__restrict__ qS,
+                                                                                     double *__restrict__ bp) {
+  __shared__ BpShared sh;
+  constexpr int NCH = BLOCK ? 9 : 6;
+  const int nt = (sd.n + kBpTile - 1) / kBpTile;
+  const int P = sd.bp_parts;
+  int item;
+  if (!xcd_item(nt * nt * P, item)) return;
+  const int ti = item / P, part = item - ti * P;  // the XCD's tiles, every part of each
+  const int t = as_const(sd.tile_order)[ti];
+  const int tile_y = t / nt, tile_x = t - tile_y * nt;
+  const int vb = part * sd.bp_part_views, ve = min(sd.n_views, vb + sd.bp_part_views);
+  double acc[NCH];
+  back_accumulate<NCH, false, true, COPY>(sd, tile_x, tile_y, qS, 0, acc, sh, vb, ve);
+  int tx, ty;
+  bp_pixel_of_thread(threadIdx.x, tx, ty);
+  const int ix = tile_x * kBpTile + tx, iy = tile_y * kBpTile + ty;
+  if (ix >= sd.n || iy >= sd.n) return;
+  const size_t nn = (size_t)sd.n * sd.n, k = (size_t)iy * sd.n + ix;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) bp[((size_t)part * NCH + c) * nn + k] = acc[c];
+}
+
+template <bool BLOCK, bool PACK>
+__global__ void __launch_bounds__(256) k_primal_combine(ScanDesc sd, const double *__restrict__ bp, float *__restrict__ f,
+                                                        float *__restrict__ fbar, float lambda, float4 *__restrict__ pk_xy,
+                                                        float4 *__restrict__ pk_yx) {
+  __shared__ float4 tile[kBpTile][kBpTile + 1];
+  __shared__ double2 red[kBpThreads / 64];
+  constexpr int NCH = BLOCK ? 9 : 6;
+  const int nt = (sd.n + kBpTile - 1) / kBpTile;
+  int item;
+  if (!xcd_item(nt * nt, item)) return;
+  const int t = as_const(sd.tile_order)[item];
+  const int tile_y = t / nt, tile_x = t - tile_y * nt;
+  int tx, ty;
+  bp_pixel_of_thread(threadIdx.x, tx, ty);
+  const int ix = tile_x * kBpTile + tx, iy = tile_y * kBpTile + ty;
+  double acc[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
+  if (ix < sd.n && iy < sd.n) {
+    const size_t nn = (size_t)sd.n * sd.n, k = (size_t)iy * sd.n + ix;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = bp[(size_t)c * nn + k];
+    for (int p = 1; p < sd.bp_parts; ++p)
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) acc[c] += bp[((size_t)p * NCH + c) * nn + k];
+  }
+  primal_epilogue<BLOCK, PACK>(sd, acc, f, fbar, lambda, tile_x, tile_y, tile, red, PrimalEpilogue{pk_xy, pk_yx, nullptr});
+}
+
 // ---------------------------------------------------------------- D_TPL
 
 template <bool PB>
@@ -269,10 +328,34 @@ hipError_t launch_spectral_dual(const ScanDesc &sd, const float *p, const float 
 }
 
 hipError_t launch_back_primal(const ScanDesc &sd, const float *qS, float *f, float *fbar, float lambda, bool block,
-                              void *pack, hipStream_t st) {
+                              void *pack, double *bp, hipStream_t st) {
   const size_t np = (size_t)sd.n + 2 * kPad;
   float4 *pk_xy = reinterpret_cast<float4 *>(pack);
   float4 *pk_yx = pack ? pk_xy + np * np : nullptr;
+  if (sd.bp_parts > 1 && !sd.bp_wide) {
+    if (!bp) return hipErrorInvalidValue;
+    const int nt = (sd.n + kBpTile - 1) / kBpTile;
+    const unsigned items = (unsigned)(nt * nt * sd.bp_parts);
+    const dim3 pgrid((items + kXcds - 1) / kXcds * kXcds);
+#define OSSCIR_BPART(B, C) hipLaunchKernelGGL((k_back_partial<B, C>), pgrid, dim3(256), 0, st, sd, qS, bp)
+#define OSSCIR_BCOMB(B, P) \
+  hipLaunchKernelGGL((k_primal_combine<B, P>), pix_grid(sd), dim3(256), 0, st, sd, bp, f, fbar, lambda, pk_xy, pk_yx)
+    if (block) {
+      if (sd.bp_copy) OSSCIR_BPART(true, true); else OSSCIR_BPART(true, false);
+    } else {
+      if (sd.bp_copy) OSSCIR_BPART(false, true); else OSSCIR_BPART(false, false);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (block) {
+      if (pack) OSSCIR_BCOMB(true, true); else OSSCIR_BCOMB(true, false);
+    } else {
+      if (pack) OSSCIR_BCOMB(false, true); else OSSCIR_BCOMB(false, false);
+    }
+#undef OSSCIR_BCOMB
+#undef OSSCIR_BPART
+    return hipGetLastError();
+  }
 #define OSSCIR_BP(B, W, P, C)                                                                                   \
   hipLaunchKernelGGL((k_back_primal<B, W, P, C>), pix_grid(sd), dim3(256), 0, st, sd, qS, f, fbar, lambda, pk_xy, \
                      pk_yx)

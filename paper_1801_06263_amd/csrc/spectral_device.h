@@ -499,13 +499,14 @@ struct PrimalEpilogue {
   double2 *partial;  // this tile's (sum |f' - f|^2, sum |f'|^2), or null
 };
 
-template <bool BLOCK, bool WIDE, bool EPI, bool COPY>
-__device__ __forceinline__ void back_primal_tile(const ScanDesc &sd, const float *__restrict__ qS,
-                                                 float *__restrict__ f, float *__restrict__ fbar, float lambda,
-                                                 int tile_x, int tile_y, BpShared &sh, const PrimalEpilogue &epi) {
-  constexpr int NCH = BLOCK ? 9 : 6;
-  double acc[NCH];
-  back_accumulate<NCH, WIDE, true, COPY>(sd, tile_x, tile_y, qS, 0, acc, sh);
+// The primal step of one tile from its FP64 back-projected sums acc (the
+// pixel of this thread); every thread of the workgroup calls it (EPI holds a
+// workgroup barrier).  tile and red: LDS the workgroup's gather is done with.
+template <bool BLOCK, bool EPI>
+__device__ __forceinline__ void primal_epilogue(const ScanDesc &sd, const double *acc, float *__restrict__ f,
+                                                float *__restrict__ fbar, float lambda, int tile_x, int tile_y,
+                                                float4 (&tile)[kBpTile][kBpTile + 1], double2 *red,
+                                                const PrimalEpilogue &epi) {
   int tx, ty;
   bp_pixel_of_thread(threadIdx.x, tx, ty);
   const int ix = tile_x * kBpTile + tx;
@@ -555,24 +556,37 @@ __device__ __forceinline__ void back_primal_tile(const ScanDesc &sd, const float
       d2 += __shfl_xor(d2, o, 64);
       n2 += __shfl_xor(n2, o, 64);
     }
-    if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = make_double2(d2, n2);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_double2(d2, n2);
   }
-  sh.tile[ty][tx] = v4;  // the gather's closing barrier has released the staging slots
+  tile[ty][tx] = v4;  // the gather's closing barrier has released the staging slots
   __syncthreads();
   {
     const int cx = threadIdx.x / kBpTile, ry = threadIdx.x & (kBpTile - 1);  // column cx, row ry of the tile
     const int jx = tile_x * kBpTile + cx, jy = tile_y * kBpTile + ry;
-    if (jx < sd.n && jy < sd.n) epi.pk_yx[(size_t)(jx + kPad) * np + (jy + kPad)] = sh.tile[ry][cx];
+    if (jx < sd.n && jy < sd.n) epi.pk_yx[(size_t)(jx + kPad) * np + (jy + kPad)] = tile[ry][cx];
   }
   if (sums && threadIdx.x == 0) {
-    double2 s = sh.red[0];
+    double2 s = red[0];
 #pragma unroll
     for (int w = 1; w < kBpThreads / 64; ++w) {
-      s.x += sh.red[w].x;
-      s.y += sh.red[w].y;
+      s.x += red[w].x;
+      s.y += red[w].y;
     }
     *epi.partial = s;
   }
+}
+
+// Back-projection of one tile fused with its primal step.  FOLD: the sum
+// over views formed part by part (ScanDesc::bp_part_views), the bits of the
+// split back-projection (k_back_partial + k_primal_combine).
+template <bool BLOCK, bool WIDE, bool EPI, bool COPY, bool FOLD = false>
+__device__ __forceinline__ void back_primal_tile(const ScanDesc &sd, const float *__restrict__ qS,
+                                                 float *__restrict__ f, float *__restrict__ fbar, float lambda,
+                                                 int tile_x, int tile_y, BpShared &sh, const PrimalEpilogue &epi) {
+  constexpr int NCH = BLOCK ? 9 : 6;
+  double acc[NCH];
+  back_accumulate<NCH, WIDE, true, COPY, FOLD>(sd, tile_x, tile_y, qS, 0, acc, sh, 0, sd.n_views);
+  primal_epilogue<BLOCK, EPI>(sd, acc, f, fbar, lambda, tile_x, tile_y, sh.tile, sh.red, epi);
 }
 
 }  // namespace osscir

@@ -62,6 +62,7 @@ SIGNATURES = {
     "osscir_plan_destroy": (c_int32, [c_void_p]),
     "osscir_plan_set_energy_sums": (c_int32, [c_void_p, c_int32]),
     "osscir_workspace_bytes": (c_int32, [c_void_p, ctypes.POINTER(c_size_t)]),
+    "osscir_batch_workspace_bytes": (c_int32, [c_void_p, ctypes.POINTER(c_size_t)]),
     "osscir_ray_lengths": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "osscir_ray_table": (c_int32, [ctypes.POINTER(_Geometry), _dp, _dp]),
     "osscir_forward_project": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
@@ -197,6 +198,8 @@ class Plan:
         nb = c_size_t()
         _check(lib.osscir_workspace_bytes(self._h, ctypes.byref(nb)))
         self.workspace_bytes = int(nb.value)
+        _check(lib.osscir_batch_workspace_bytes(self._h, ctypes.byref(nb)))
+        self.batch_workspace_bytes = int(nb.value)  # a batch slot's (at most workspace_bytes)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -227,9 +230,10 @@ class Plan:
         import torch
         return torch.empty(*shape, dtype=dtype or torch.float32, device="cuda")
 
-    def workspace(self):
+    def workspace(self, batch: bool = False):
         import torch
-        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
+        return torch.empty(self.batch_workspace_bytes if batch else self.workspace_bytes, dtype=torch.uint8,
+                           device="cuda")
 
     # -- entry points
     def ray_lengths(self, stream=None):
@@ -277,15 +281,16 @@ class Plan:
                   _dev(work), work.numel(), _stream_handle(stream)))
         return sigma, img
 
-    def new_state(self, c, f0=None):
+    def new_state(self, c, f0=None, batch: bool = False):
         """Device state for MOCCA from counts c [4, V, D] (a tensor or a host
-        array; f0 = fbar0 = f0 or 0, y0 = 0)."""
+        array; f0 = fbar0 = f0 or 0, y0 = 0).  batch: with the smaller
+        workspace of a batch slot (then for batch slots only)."""
         import torch
         f = torch.zeros(3, self.n, self.n, dtype=torch.float32, device="cuda") if f0 is None \
             else f0.to(device="cuda", dtype=torch.float32).contiguous().clone()
         c = torch.as_tensor(np.ascontiguousarray(c, dtype=np.float32)) if isinstance(c, np.ndarray) else c
         return State(f=f, fbar=f.clone(), y=torch.zeros(4, *self.sino_shape, dtype=torch.float32, device="cuda"),
-                     c=c.to(device="cuda", dtype=torch.float32).contiguous(), work=self.workspace())
+                     c=c.to(device="cuda", dtype=torch.float32).contiguous(), work=self.workspace(batch))
 
     def _c_state(self, state: State) -> _State:
         import torch

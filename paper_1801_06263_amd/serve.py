@@ -135,13 +135,14 @@ class Server:
         plan if no admitted request has used that scan yet."""
         plan = self.plans.get((req.geom, spectral_key(req.spec)))
         if plan is not None:
-            return request_bytes(req.geom, plan.workspace_bytes, req.n_inner)
+            return request_bytes(req.geom, plan.batch_workspace_bytes, req.n_inner)
         return plan_bytes(req.geom) + request_bytes(req.geom, self._estimate_workspace(req.geom), req.n_inner)
 
     @staticmethod
     def _estimate_workspace(geom) -> int:
-        """Upper bound of osscir_workspace_bytes before the plan exists: p and
-        qS (12 FP32 per ray), the D_TPL partial sums and the packed images."""
+        """Upper bound of a batch slot's workspace (osscir_batch_workspace_bytes)
+        before the plan exists: p and qS (12 FP32 per ray), the D_TPL partial
+        sums and the packed images."""
         L = geom.n_views * geom.n_bins
         np_ = geom.n + 8
         return 48 * L + 8 * ((L + 255) // 256) + 32 * np_ * np_ + 4 * 256
@@ -156,10 +157,10 @@ class Server:
         plan = self._plan(req)
         if plan is None:
             return False
-        cost = request_bytes(req.geom, plan.workspace_bytes, req.n_inner)
+        cost = request_bytes(req.geom, plan.batch_workspace_bytes, req.n_inner)
         if self.used + cost > self.hbm_budget:
             return False
-        state = plan.new_state(req.counts)
+        state = plan.new_state(req.counts, batch=True)
         slot = self.free_slots.pop()
         nested = {"n_inner": req.n_inner} if req.n_inner > 1 else {}
         self.batch.set_slot(slot, plan, state, req.lam, max_iter=req.max_iter, tol=req.tol, **nested)

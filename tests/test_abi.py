@@ -45,6 +45,7 @@ def test_errors_are_reported_without_a_device():
     assert rc == -1 and b"plan" in lib.osscir_last_error()
     nb = ctypes.c_size_t()
     assert lib.osscir_workspace_bytes(None, ctypes.byref(nb)) == -1
+    assert lib.osscir_batch_workspace_bytes(None, ctypes.byref(nb)) == -1
     # batch entry points: argument errors are reported before any device work
     assert lib.osscir_batch_destroy(None) == 0
     h = ctypes.c_void_p()

@@ -246,6 +246,35 @@ def test_tuner_leaves_trajectories_unchanged(scans):
         assert same_state(st, single_run(plan, c, Params(lam_of(pr), "block", "clip", True), 6)), pr.name
 
 
+def test_split_back_projection_scans_in_a_batch_with_slot_workspaces(scans):
+    """Scans of few 16 x 16 tiles split their single-scan back-projection
+    over views (per-part FP64 sums in the workspace, added in order); a batch
+    slot forms the same sums in registers, so it needs the smaller workspace
+    osscir_batch_workspace_bytes and still equals the scan run alone."""
+    from paper_1801_06263_amd import Batch, Params
+    from paper_1801_06263_amd.osscir import OsscirError
+    n_it = 9
+    modes = Params(1.0, "block", "clip", True)
+    b = Batch(modes, 4)
+    states = []
+    for i, (pr, plan, c) in enumerate(scans):
+        assert plan.batch_workspace_bytes <= plan.workspace_bytes
+        st = plan.new_state(c, batch=True)
+        b.set_slot(i, plan, st, lam_of(pr))
+        states.append(st)
+    assert any(plan.batch_workspace_bytes < plan.workspace_bytes for _, plan, _ in scans)  # some scan splits
+    b.iterate(n_it)
+    for i, (pr, plan, c) in enumerate(scans):
+        ref = single_run(plan, c, Params(lam_of(pr), "block", "clip", True), n_it)
+        assert same_state(states[i], ref), pr.name
+    # a workspace one byte short of a slot's is refused
+    pr, plan, c = scans[0]
+    st = plan.new_state(c, batch=True)
+    st.work = st.work[:plan.batch_workspace_bytes - 1]
+    with pytest.raises(OsscirError, match="workspace"):
+        b.set_slot(0, plan, st, lam_of(pr))
+
+
 def test_batched_slot_matches_oracle():
     """The tiny scan run inside a batch (beside a 128^2 slice) for 100
     iterations against the FP64 oracle's trajectory."""

@@ -16,8 +16,9 @@ class FakePlan:
         self.n, self.n_views, self.n_bins = geom.n, geom.n_views, geom.n_bins
         L = geom.n_views * geom.n_bins
         self.workspace_bytes = 48 * L + 8 * ((L + 255) // 256) + 32 * (geom.n + 8) ** 2
+        self.batch_workspace_bytes = self.workspace_bytes
 
-    def new_state(self, c):
+    def new_state(self, c, batch=False):
         return types.SimpleNamespace(f=("f", id(c)))
 
     def close(self):
