@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--workload", default="large", choices=["tiny", "medium", "large"])
     ap.add_argument("--precond", default="block", choices=["block", "diag"])
     ap.add_argument("--curvature", default="clip", choices=["clip", "window"])
-    ap.add_argument("--fp64-small", type=int, default=1)
+    ap.add_argument("--fp64-small", type=int, default=0)
     ap.add_argument("--energy-sums", default="auto", choices=["auto", "vector"],
                     help="vector: the spectral step's energy sums as per-ray vector FMAs instead of the "
                          "matrix-core contraction the plan picks where it applies")

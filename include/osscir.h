@@ -99,9 +99,11 @@ typedef struct {
 /* Step-size ratio lambda > 0 (Sec. II: "a step size ratio parameter that must
  * be tuned"), preconditioner and curvature choice, and whether the per-ray
  * tail (3x3 eigen-clip, 4x4 dual solve) runs in FP64 (fp64_small = 1) or FP32
- * (0).  Projection weights, line integrals and energy sums are FP32 in both
- * cases; back-projection sums over views and the per-pixel 3x3 solve are
- * always FP64 (the 3x3 step blocks are ill-conditioned). */
+ * (0; the 3x3 Gram inverse of the clipped-curvature dual step is FP64 in both,
+ * which keeps the FP32 tail within 1e-3 of the FP64 oracle's maps).
+ * Projection weights, line integrals and energy sums are FP32 in both cases;
+ * back-projection sums over views and the per-pixel 3x3 solve are always
+ * FP64 (the 3x3 step blocks are ill-conditioned). */
 typedef struct {
   double lambda;
   int32_t precond;
