@@ -304,7 +304,9 @@ int osscir_material_transform(const double *M, const float *in, float *out, int3
  * A slot stops by itself once it has run max_iter iterations (if > 0) or
  * once the relative change ||f_{n+1} - f_n||_2 / ||f_{n+1}||_2 (FP64, over
  * the three maps) is <= tol (if > 0); a stopped slot keeps its last iterate
- * and costs nothing further.  A batch is used from one host thread, with one
+ * and costs nothing further.  A slot whose maps stop being finite (a NaN or
+ * an infinity in f, from non-finite inputs or a diverging step) stops after
+ * that iteration with OSSCIR_SLOT_FAILED, the other slots unaffected.  A batch is used from one host thread, with one
  * stream for all its calls.  Batch calls synchronise where stated.
  * ------------------------------------------------------------------------ */
 typedef struct osscir_batch_s *osscir_batch;
@@ -312,6 +314,7 @@ typedef struct osscir_batch_s *osscir_batch;
 #define OSSCIR_SLOT_EMPTY 0
 #define OSSCIR_SLOT_RUNNING 1
 #define OSSCIR_SLOT_DONE 2
+#define OSSCIR_SLOT_FAILED 3
 
 typedef struct {
   int32_t state;      /* OSSCIR_SLOT_* */

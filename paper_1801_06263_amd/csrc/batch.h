@@ -7,7 +7,7 @@
 
 namespace osscir {
 
-constexpr int kSlotEmpty = 0, kSlotRunning = 1, kSlotDone = 2;
+constexpr int kSlotEmpty = 0, kSlotRunning = 1, kSlotDone = 2, kSlotFailed = 3;
 constexpr int kMaxSlots = 256;
 constexpr int kItemSlotShift = 24;  // work item = slot << 24 | item index within the slot (as unsigned bits)
 constexpr int kItemLocalMask = (1 << kItemSlotShift) - 1;
@@ -43,8 +43,9 @@ struct SlotDesc {
 
 // Device-owned progress of a slot.  The end-of-iteration kernel advances
 // iters, stores the relative change of f and marks the slot done once
-// iters reaches max_iter (> 0) or the change falls to tol (> 0); the stage
-// kernels skip slots that are not running.
+// iters reaches max_iter (> 0) or the change falls to tol (> 0), or failed
+// once f is no longer finite; the stage kernels skip slots that are not
+// running.
 struct SlotStatus {
   int state;
   int iters;

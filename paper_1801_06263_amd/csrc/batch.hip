@@ -170,7 +170,9 @@ __global__ void __launch_bounds__(64) kb_tick(const SlotDesc *__restrict__ slots
     SlotStatus st = status[s];
     st.iters += 1;
     st.rel_change = n2 > 0.0 ? sqrt(d2 / n2) : (d2 > 0.0 ? INFINITY : 0.0);
-    if ((st.max_iter > 0 && st.iters >= st.max_iter) || (st.tol > 0.0 && st.rel_change <= st.tol))
+    if (!isfinite(d2) || !isfinite(n2))  // a NaN or an infinity in f (or f - f_prev): stop and report
+      st.state = kSlotFailed;
+    else if ((st.max_iter > 0 && st.iters >= st.max_iter) || (st.tol > 0.0 && st.rel_change <= st.tol))
       st.state = kSlotDone;
     status[s] = st;
   }

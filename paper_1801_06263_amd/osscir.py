@@ -54,7 +54,7 @@ class _BatchConfig(ctypes.Structure):
                 ("bp_wgs", c_int32), ("bp_xcd", c_int32)]
 
 
-SLOT_EMPTY, SLOT_RUNNING, SLOT_DONE = 0, 1, 2
+SLOT_EMPTY, SLOT_RUNNING, SLOT_DONE, SLOT_FAILED = 0, 1, 2, 3
 
 # name -> (restype, argtypes) for every entry point of include/osscir.h
 SIGNATURES = {

@@ -49,6 +49,7 @@ class Result:
     arrival: float
     admitted: float
     finished: float
+    failed: bool = False    # stopped because its maps stopped being finite (f holds the last iterate)
 
     @property
     def latency(self) -> float:
@@ -178,8 +179,8 @@ class Server:
         done = []
         for slot, (req, state, t_adm, cost) in list(self.active.items()):
             st, iters, rel = status[slot]
-            if st == 2:  # stopped by its rule
-                done.append(Result(req.rid, state.f, iters, rel, req.arrival, t_adm, t))
+            if st in (2, 3):  # stopped by its rule, or failed (non-finite maps)
+                done.append(Result(req.rid, state.f, iters, rel, req.arrival, t_adm, t, failed=st == 3))
                 self.batch.clear_slot(slot)
                 del self.active[slot]
                 self.free_slots.append(slot)
@@ -224,6 +225,7 @@ def latency_summary(results: List[Result], makespan: float) -> dict:
     iters = np.array([r.iters for r in results])
     return {
         "requests": len(results),
+        "failed": sum(1 for r in results if r.failed),
         "solves_per_s": round(len(results) / makespan, 4) if makespan > 0 else None,
         "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
         "p99_latency_s": round(float(np.percentile(lat, 99)), 4),

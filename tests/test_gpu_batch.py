@@ -275,6 +275,27 @@ def test_split_back_projection_scans_in_a_batch_with_slot_workspaces(scans):
         b.set_slot(0, plan, st, lam_of(pr))
 
 
+def test_slot_with_non_finite_counts_fails_alone(scans):
+    """A slot whose counts hold a NaN (on a ray through the image) stops with
+    SLOT_FAILED after its first iteration, its maps no longer finite; the
+    other slot runs on and still equals its scan run alone."""
+    from paper_1801_06263_amd import Batch, Params
+    from paper_1801_06263_amd.osscir import SLOT_FAILED, SLOT_RUNNING
+    (pr0, plan0, c0), (pr1, plan1, c1) = scans[0], scans[1]
+    bad = c0.clone()
+    bad[0, 0, bad.shape[2] // 2] = float("nan")  # view 0's central bin
+    b = Batch(Params(1.0, "block", "clip", True), 2)
+    s0, s1 = plan0.new_state(bad), plan1.new_state(c1)
+    b.set_slot(0, plan0, s0, lam_of(pr0), tol=1e-12)
+    b.set_slot(1, plan1, s1, lam_of(pr1))
+    b.iterate(5)
+    status = b.status()
+    assert status[0][:2] == (SLOT_FAILED, 1), status[0]
+    assert not torch.isfinite(s0.f).all()
+    assert status[1][:2] == (SLOT_RUNNING, 5), status[1]
+    assert same_state(s1, single_run(plan1, c1, Params(lam_of(pr1), "block", "clip", True), 5))
+
+
 def test_batched_slot_matches_oracle():
     """The tiny scan run inside a batch (beside a 128^2 slice) for 100
     iterations against the FP64 oracle's trajectory."""

@@ -38,7 +38,7 @@ class FakeBatch:
 
     def set_slot(self, slot, plan, state, lam, max_iter=0, tol=0.0):
         assert slot not in self.slots and 0 <= slot < self.max_slots
-        self.slots[slot] = [0, max_iter]
+        self.slots[slot] = [0, max_iter, lam != lam]  # a NaN step ratio stands for a slot that fails
         self.max_active = max(self.max_active, len(self.slots))
 
     def clear_slot(self, slot):
@@ -46,13 +46,13 @@ class FakeBatch:
 
     def iterate(self, n, use_graph=True):
         for v in self.slots.values():
-            v[0] = min(v[0] + n, v[1])
+            v[0] = 1 if v[2] else min(v[0] + n, v[1])
         self.clock.t += 0.001 * n * len(self.slots) ** 0.5
 
     def status(self):
         out = [(0, 0, 0.0)] * self.max_slots
-        for s, (it, mx) in self.slots.items():
-            out[s] = (2 if it >= mx else 1, it, 0.0)
+        for s, (it, mx, bad) in self.slots.items():
+            out[s] = (3 if bad and it else (2 if it >= mx else 1), it, 0.0)
         return out
 
     def close(self):
@@ -96,6 +96,23 @@ def test_every_request_completes_at_its_budget():
         assert r.iters == by_id[r.rid].max_iter
         assert r.arrival <= r.admitted <= r.finished
     assert srv.used == sum(plan_bytes(g) for g, _ in srv.plans)
+    assert not srv.active and len(srv.free_slots) == 4
+
+
+def test_failed_request_is_retired_and_reported():
+    """A request whose slot fails (maps no longer finite) is retired after
+    the tick that saw it, flagged, and its slot and bytes are reused; the
+    other requests run to their budgets."""
+    import dataclasses
+    reqs = requests()
+    reqs[3] = dataclasses.replace(reqs[3], lam=float("nan"))
+    srv, res, clock = serve(reqs, max_slots=4, iters_per_tick=5)
+    assert sorted(r.rid for r in res) == [r.rid for r in reqs]
+    by_id = {r.rid: r for r in reqs}
+    for r in res:
+        assert r.failed == (r.rid == 3)
+        assert r.iters == (1 if r.failed else by_id[r.rid].max_iter)
+    assert latency_summary(res, clock.t)["failed"] == 1
     assert not srv.active and len(srv.free_slots) == 4
 
 
